@@ -1,0 +1,24 @@
+"""Plain FP64 CPU oracle for group-wise Naive Bayes malware detection
+(Sahay & Chaudhari, "An Efficient Detection of Malware by Naive Bayes
+Classifier Using GPGPU", 2019).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, obviously correct
+definition that the GPU library is checked against.  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product library never does, and it shares no code with the HIP path.
+
+Modules
+  nb         training counts, Laplace-smoothed log tables, joint log-likelihood
+             scores, decision rule and posteriors (section 4, posterior equation
+             and the malware/benign decision that follows it)
+  groups     size-group model validity and fallback routing (section 4, the
+             fewer-than-six-files rule and the next-group fallback)
+  precision  reduced-precision mirrors: BF16 and FP32 round-to-nearest-even
+             from FP64, FP8-e4m3 quantisation of counts, certified label bands
+
+Parity status: every function here is pinned by the not-gpu tests (worked
+example, exact rationals, library cross-checks, invariants); none is
+"parity unpinned".  The paper's own empirical results (about 87% accuracy,
+up to 200x speed-up) need its dataset and hardware and are not reproduced.
+"""
+from . import nb, groups, precision  # noqa: F401

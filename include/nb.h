@@ -1,0 +1,178 @@
+/*
+ * nb.h - C ABI of libnbgpu, a gfx950 (MI355X) library for the data-parallel
+ * hot path of group-wise Naive Bayes malware detection (Sahay & Chaudhari,
+ * "An Efficient Detection of Malware by Naive Bayes Classifier Using GPGPU").
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status: NB_OK (0) or a negative NB_E*
+ *     code; nb_last_error() then holds a message for the calling thread.
+ *     Nothing throws across this boundary.
+ *   - Pointers named x, y, labels, log_post, scores, workspace and model->dev
+ *     are DEVICE pointers on the current HIP device; the caller owns all of
+ *     them.  Host pointers are named *_host.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it and the call returns; outputs are valid once the
+ *     stream has completed it.  Argument errors are returned before anything
+ *     is enqueued.
+ *   - Feature matrices are row-major [n rows (files) x F features] with a row
+ *     stride of `ld` ELEMENTS (ld >= F).  The buffer must hold
+ *     (n - 1) * ld + F elements.  Features are non-negative occurrence counts
+ *     (the paper's per-file opcode occurrences, section 3); scoring does not
+ *     re-validate them.
+ *   - Class labels: 0 = benign, 1 = malware for the two-class detector;
+ *     exact ties are decided for the lowest class index (section 4: malware
+ *     only if its posterior is higher, otherwise benign).
+ */
+#ifndef NB_H
+#define NB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define NB_OK          0
+#define NB_EINVAL     -1  /* bad argument (shape, type, NULL, alpha <= 0, ...)  */
+#define NB_EOVERFLOW  -2  /* a count would not fit its exact integer type      */
+#define NB_EMINFILES  -3  /* a class has fewer training files than required    */
+#define NB_ENOMODEL   -4  /* no group has a trained model to fall back on      */
+#define NB_EDATA      -5  /* label outside [0, C) or negative feature value     */
+#define NB_ENOMEM     -6  /* workspace or arena too small                       */
+#define NB_EHIP       -7  /* a HIP runtime call failed                           */
+#define NB_EREJECTED  -8  /* serving: request can never fit the arena           */
+
+/* Naive Bayes variant.  The paper does not name one (section 4); both
+ * classical forms over occurrence counts are provided. */
+#define NB_MULTINOMIAL 0  /* P(x|c) = prod_f theta_cf^x_f (occurrences)        */
+#define NB_BERNOULLI   1  /* P(x|c) = prod_f theta_cf^b_f (1-theta_cf)^(1-b_f), b = x > 0 */
+
+/* Feature element types. */
+#define NB_X_U8   0       /* uint8 counts (clipped at 255 by the producer)       */
+#define NB_X_I32  1       /* int32 counts                                         */
+#define NB_X_FP8  2       /* OCP FP8-e4m3 (e4m3fn) bytes of quantised counts      */
+
+/* Scoring table precision (accumulation is always FP32). */
+#define NB_W_F32  0       /* table rounded once from FP64 to FP32 (plain path)   */
+#define NB_W_BF16 1       /* table rounded once from FP64 to BF16                */
+
+/* nb_train flags */
+#define NB_TRAIN_ASYNC 1  /* do not synchronise; read the outcome later with
+                             nb_model_status() */
+
+const char* nb_version(void);
+/* Message for the last error on this thread ("" if none). */
+const char* nb_last_error(void);
+
+/* ------------------------------------------------------------------ model
+ * A model is a position-independent byte buffer in device memory, owned by
+ * the caller (any allocator), of nb_model_bytes(C, F) bytes, 256-byte
+ * aligned.  It holds the exact training counts (the model's real state: the
+ * tables are a pure function of them), the FP64 table and the FP32/BF16
+ * scoring tables.  Offsets of each part are given by nb_model_layout(). */
+typedef struct {
+  int32_t kind;        /* NB_MULTINOMIAL or NB_BERNOULLI                       */
+  int32_t n_classes;   /* C, 2 .. 256                                           */
+  int32_t n_features;  /* F, 1 .. 1048576                                       */
+  int32_t trained;     /* set to 1 by a successful synchronous nb_train         */
+  void*   dev;         /* device buffer of nb_model_bytes(C, F) bytes           */
+} nb_model;
+
+typedef struct {
+  size_t  total_bytes;
+  int32_t padded_features;  /* Fp: F rounded up to a multiple of 1024          */
+  int32_t form_rows;        /* P: 1 (two classes: log-odds row) or C            */
+  size_t  off_status;       /* int32[4]: status, trained flag, reserved         */
+  size_t  off_class_totals; /* int64[C]  N_c: training files per class          */
+  size_t  off_class_sums;   /* int64[C]  S_c: sum_f T_cf (multinomial) or N_c   */
+  size_t  off_counts;       /* int32[C*F] T_cf (occurrences) or D_cf (presence) */
+  size_t  off_log_theta;    /* double[C*F] log theta_cf                          */
+  size_t  off_log_1m_theta; /* double[C*F] log(1 - theta_cf) (Bernoulli)        */
+  size_t  off_weight;       /* double[C*F] W: scorer weights, s = bias + g(x).W^T */
+  size_t  off_bias;         /* double[C]   bias_c (log prior [+ sum log(1-theta)]) */
+  size_t  off_form_f32;     /* float[(P+1)*Fp] scoring rows, FP32, zero padded  */
+  size_t  off_form_bf16;    /* uint16[(P+1)*Fp] the same rows rounded to BF16   */
+  size_t  off_form_bias;    /* float[P+1] biases of the scoring rows            */
+  double  alpha;            /* unused by the layout; kept for ABI growth         */
+} nb_layout;
+
+/* Bytes of a model buffer; 0 if C or F is out of range. */
+size_t nb_model_bytes(int32_t n_classes, int32_t n_features);
+/* Fill *out with the model buffer layout for (C, F).
+ * The scoring rows restate the weight form without changing posteriors:
+ * for C = 2 row 0 is W_1 - W_0 (the log-odds) and the aux row is W_0; for
+ * C > 2 row c is W_c - mean_c W and the aux row is the mean.  Every row is
+ * computed in FP64 and rounded once. */
+int nb_model_layout(int32_t n_classes, int32_t n_features, nb_layout* out);
+
+/* ------------------------------------------------------------------ train
+ * Section 4: fit one Naive Bayes model on labelled training files.
+ *   N_c  = #{i : y_i = c}                                  (exact, int64)
+ *   T_cf = sum_{i: y_i = c} x_if   (multinomial)           (exact, int32)
+ *   D_cf = #{i : y_i = c, x_if > 0} (Bernoulli)            (exact, int32)
+ *   log prior_c = log N_c - log N   (empirical)
+ *   multinomial: log theta_cf = log(T_cf + a) - log(S_c + a F)
+ *   Bernoulli:   log theta_cf = log(D_cf + a) - log(N_c + 2a),
+ *                log(1-theta) = log(N_c - D_cf + a) - log(N_c + 2a)
+ * in FP64 on the device, then the FP32/BF16 scoring rows (round once).
+ * x: [n x F] features (NB_X_U8 or NB_X_I32), y: int32[n] labels.
+ * alpha > 0 (Laplace smoothing when 1).  min_files_per_class >= 1: a class
+ * with fewer files fails with NB_EMINFILES (the paper's rule uses 6).
+ * workspace: device scratch of at least nb_train_workspace_bytes(...) bytes.
+ * Errors: NB_EINVAL (arguments), NB_EOVERFLOW (n*255 > INT32_MAX for bytes,
+ * or a count above INT32_MAX for int32 features), NB_EDATA (label outside
+ * [0, C) or negative feature), NB_EMINFILES.  Device-detected errors are
+ * reported after the stream is synchronised (the default), or by
+ * nb_model_status() with NB_TRAIN_ASYNC. */
+size_t nb_train_workspace_bytes(int32_t n_classes, int32_t n_features, int64_t n, int32_t xtype);
+int nb_train(nb_model* model, const void* x, int32_t xtype, int64_t n, int64_t ld,
+             const int32_t* y, double alpha, int32_t min_files_per_class,
+             void* workspace, size_t workspace_bytes, int32_t flags, void* stream);
+/* Synchronise `stream` and return the device-side outcome of the last
+ * nb_train on this model (NB_OK, NB_EDATA, NB_EOVERFLOW, NB_EMINFILES);
+ * sets model->trained accordingly. */
+int nb_model_status(nb_model* model, void* stream);
+
+/* ------------------------------------------------------------------ score
+ * Section 4: per-file joint log-likelihoods s_c = bias_c + sum_f g(x_f) W_cf
+ * (g = identity for multinomial, 1[x > 0] for Bernoulli; the class-constant
+ * multinomial coefficient is omitted), the label (highest posterior, ties to
+ * the lowest class index) and the log posteriors s_c - logsumexp_c s_c.
+ * x: [n x F] features of type xtype; wtype selects the FP32 or BF16 table;
+ * accumulation is FP32.  Outputs (device, any may be NULL but not all):
+ *   labels int32[n], log_post float[n x C], scores float[n x C] (raw s_c).
+ * n == 0 is a no-op.  The per-file summation order depends only on (F, C,
+ * xtype, wtype), never on n or on other files. */
+int nb_score(const nb_model* model, const void* x, int32_t xtype, int64_t n, int64_t ld,
+             int32_t wtype, int32_t* labels, float* log_post, float* scores, void* stream);
+
+/* ------------------------------------------------------------- features
+ * FP8-e4m3 encoding of byte counts: q = RNE_e4m3fn(min(x, 240)).
+ * x: uint8 [n x F] (stride ld_x), out: uint8 [n x F] (stride ld_out). */
+int nb_quantize_fp8(const uint8_t* x, int64_t n, int32_t n_features, int64_t ld_x,
+                    uint8_t* out, int64_t ld_out, void* stream);
+
+/* ----------------------------------------------------------- size groups
+ * Sections 3-4: group g has a model iff every class has >= min_files
+ * training files; an untrained group's files are scored by the next trained
+ * group (first trained index above), or, where none is above, the nearest
+ * trained group below.  class_counts_host: int64[G x C]; route_host: int32[G]
+ * receives the index of the group whose model scores group g.  Host only.
+ * Errors: NB_EINVAL, NB_ENOMODEL (no group trained). */
+int nb_route_groups(const int64_t* class_counts_host, int32_t n_groups, int32_t n_classes,
+                    int32_t min_files, int32_t* route_host);
+
+/* ---------------------------------------------------------------- probe
+ * Read-only streaming kernel used to measure achievable HBM bandwidth:
+ * reads `bytes` bytes (multiple of 16) at `src` and writes one uint32 per
+ * workgroup to sink (>= nb_probe_sink_words() words).  Not part of the
+ * method; measurement support. */
+int32_t nb_probe_sink_words(void);
+int nb_probe_read(const void* src, int64_t bytes, uint32_t* sink, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NB_H */

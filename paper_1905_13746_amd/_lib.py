@@ -1,0 +1,91 @@
+"""ctypes declarations of libnbgpu's C ABI (include/nb.h).
+
+Loading fails loudly: there is no fallback implementation of any entry point.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnbgpu.so")
+
+NB_OK = 0
+STATUS_NAMES = {
+    -1: "NB_EINVAL", -2: "NB_EOVERFLOW", -3: "NB_EMINFILES", -4: "NB_ENOMODEL",
+    -5: "NB_EDATA", -6: "NB_ENOMEM", -7: "NB_EHIP", -8: "NB_EREJECTED",
+}
+
+MULTINOMIAL, BERNOULLI = 0, 1
+X_U8, X_I32, X_FP8 = 0, 1, 2
+W_F32, W_BF16 = 0, 1
+TRAIN_ASYNC = 1
+
+
+class NbModel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("n_features", ctypes.c_int32), ("trained", ctypes.c_int32),
+                ("dev", ctypes.c_void_p)]
+
+
+class NbLayout(ctypes.Structure):
+    _fields_ = [("total_bytes", ctypes.c_size_t), ("padded_features", ctypes.c_int32),
+                ("form_rows", ctypes.c_int32),
+                ("off_status", ctypes.c_size_t), ("off_class_totals", ctypes.c_size_t),
+                ("off_class_sums", ctypes.c_size_t), ("off_counts", ctypes.c_size_t),
+                ("off_log_theta", ctypes.c_size_t), ("off_log_1m_theta", ctypes.c_size_t),
+                ("off_weight", ctypes.c_size_t), ("off_bias", ctypes.c_size_t),
+                ("off_form_f32", ctypes.c_size_t), ("off_form_bf16", ctypes.c_size_t),
+                ("off_form_bias", ctypes.c_size_t), ("alpha", ctypes.c_double)]
+
+
+_i32, _i64, _sz, _vp, _d = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
+_PM = ctypes.POINTER(NbModel)
+
+# name -> (restype, argtypes); every symbol include/nb.h declares
+SIGNATURES = {
+    "nb_version": (ctypes.c_char_p, []),
+    "nb_last_error": (ctypes.c_char_p, []),
+    "nb_model_bytes": (_sz, [_i32, _i32]),
+    "nb_model_layout": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(NbLayout)]),
+    "nb_train_workspace_bytes": (_sz, [_i32, _i32, _i64, _i32]),
+    "nb_train": (ctypes.c_int, [_PM, _vp, _i32, _i64, _i64, _vp, _d, _i32, _vp, _sz, _i32, _vp]),
+    "nb_model_status": (ctypes.c_int, [_PM, _vp]),
+    "nb_score": (ctypes.c_int, [_PM, _vp, _i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp]),
+    "nb_quantize_fp8": (ctypes.c_int, [_vp, _i64, _i32, _i64, _vp, _i64, _vp]),
+    "nb_route_groups": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp]),
+    "nb_probe_sink_words": (_i32, []),
+    "nb_probe_read": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libnbgpu.so (built in-tree by paper_1905_13746_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1905_13746_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class NBError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = load().nb_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code: int, where: str):
+    if code != NB_OK:
+        raise NBError(code, where)
+    return code

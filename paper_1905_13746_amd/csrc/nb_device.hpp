@@ -1,0 +1,55 @@
+// Device helpers shared by the libnbgpu kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nb {
+namespace dev {
+
+// 16-byte vector with 4-byte alignment: rows of byte features are only
+// dword-aligned (row stride F bytes, F a multiple of 4), and gfx950 global
+// loads need dword alignment only.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+struct __attribute__((packed, aligned(4))) u32x4_a4 {
+  u32x4 v;
+};
+
+__device__ __forceinline__ u32x4 load16(const uint8_t* p) {
+  return reinterpret_cast<const u32x4_a4*>(p)->v;
+}
+
+// Same 16 bytes, but every byte at or beyond `avail` bytes from p reads as 0
+// (used only for the last rows of a buffer, where a full 16-byte access
+// could leave the caller's allocation).
+__device__ __forceinline__ u32x4 load16_guarded(const uint8_t* p, int64_t avail) {
+  u32x4 out = {0u, 0u, 0u, 0u};
+  if (avail >= 16) return load16(p);
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    uint32_t v = (b < avail) ? (uint32_t)p[b] : 0u;
+    out[b >> 2] |= v << (8 * (b & 3));
+  }
+  return out;
+}
+
+// Round-to-nearest-even of an FP64 value to BF16, in one rounding: add the
+// rounding increment below bit 45 of the FP64 significand (ties to even),
+// truncate, and take the (then exact) FP32 image's upper half.  Valid for the
+// normal BF16 range, which holds every table value.
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double v) {
+  uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t lsb = (b >> 45) & 1ull;
+  b += 0x00000FFFFFFFFFFFull + lsb;
+  b &= ~((1ull << 45) - 1ull);
+  const float f = (float)__longlong_as_double((long long)b);
+  return (uint16_t)(__float_as_uint(f) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+}  // namespace dev
+}  // namespace nb

@@ -1,0 +1,481 @@
+// Naive Bayes training on gfx950: exact per-class feature counts, the FP64
+// Laplace-smoothed log table and the rounded scoring rows.
+//
+// Paper, section 4: a model is trained per size group on labelled opcode
+// occurrence vectors.  The method's training is a pair of reductions,
+//   N_c  = #{i : y_i = c},
+//   T_cf = sum_{i : y_i = c} x_if      (multinomial)
+//   D_cf = #{i : y_i = c, x_if > 0}    (Bernoulli),
+// followed by C*F logarithms.  The reductions are HBM-bound (one pass over
+// the training matrix); the logarithms are negligible.
+//
+// Kernel pipeline (one stream):
+//   init_status   zero the model's status word
+//   count_kernel  grid (slot, class, chunk): each workgroup streams the rows
+//                 of ONE class inside its slot of rows and ONE 1024-feature
+//                 chunk.  Labels are read 64 at a time and compacted with a
+//                 wave ballot, so a row is loaded only by the workgroup of its
+//                 class.  Byte counts accumulate in packed 16-bit register
+//                 lanes (two features per 32-bit add), flushed to 32-bit every
+//                 <= 256 rows; four waves then combine in LDS and write one
+//                 int64 partial per (slot, class, feature) to the workspace.
+//   reduce_counts sum the partials (integer sums: exact, order-free), check
+//                 the int32 range, write T/D and N_c.
+//   class_tables  one workgroup per class: S_c, the FP64 log theta /
+//                 log(1 - theta) / weights and the bias, with a fixed-order
+//                 tree reduction (deterministic).
+//   form_rows     the scoring rows (log-odds / class-centred + aux) in FP64,
+//                 rounded once to FP32 and to BF16.
+#include <algorithm>
+#include <cmath>
+
+#include "nb_device.hpp"
+#include "nb_internal.hpp"
+
+namespace nb {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kSeg = 16;                  // features per lane per chunk
+constexpr int kChunk = 64 * kSeg;         // features per chunk (one wave)
+constexpr int kBatch = 8;                 // rows loaded together by a wave
+constexpr int kTargetUnits = 1024;        // (slot, class, chunk) workgroups aimed at
+constexpr int64_t kMinRowsPerSlot = 512;
+
+struct CountArgs {
+  const uint8_t* x;
+  int64_t ld_bytes;
+  int64_t n;
+  int64_t total_bytes;     // bytes the caller's buffer is known to hold
+  const int32_t* y;
+  int64_t rows_per_slot;
+  int64_t* part;           // [S][C][Fp]
+  int64_t* nc_part;        // [S][C]
+  int32_t* status;
+  int32_t F, C, Fp;
+};
+
+__global__ void init_status(int32_t* status) {
+  if (threadIdx.x < 4) status[threadIdx.x] = 0;
+}
+
+template <int XT, bool BIN>
+__global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
+  constexpr int EB = (XT == NB_X_I32) ? 4 : 1;   // bytes per feature
+  constexpr int NV = EB;                          // 16-byte vectors per lane per row
+  const int slot = blockIdx.x, cls = blockIdx.y, ch = blockIdx.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  const int64_t r_begin = (int64_t)slot * a.rows_per_slot;
+  const int64_t r_end = min(a.n, r_begin + a.rows_per_slot);
+  // four contiguous sub-ranges, 64-row aligned
+  const int64_t per = ((r_end - r_begin + kWaves - 1) / kWaves + 63) / 64 * 64;
+  const int64_t w_begin = min(r_end, r_begin + wave * per);
+  const int64_t w_end = min(r_end, w_begin + per);
+
+  const int f0 = ch * kChunk + lane * kSeg;       // this lane's first feature
+  const int64_t col = (int64_t)f0 * EB;
+  const int64_t chunk_end = (int64_t)min(a.Fp, (ch + 1) * kChunk) * EB;
+
+  // byte features: packed 16-bit lanes (lo: bytes 0,2; hi: bytes 1,3 of each dword)
+  uint32_t lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+  int64_t acc[kSeg];
+#pragma unroll
+  for (int e = 0; e < kSeg; ++e) acc[e] = 0;
+  int packed_rows = 0;
+  int64_t matched = 0;
+  bool bad_label = false, negative = false;
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      acc[4 * k + 0] += lo[k] & 0xFFFFu;
+      acc[4 * k + 2] += lo[k] >> 16;
+      acc[4 * k + 1] += hi[k] & 0xFFFFu;
+      acc[4 * k + 3] += hi[k] >> 16;
+      lo[k] = 0;
+      hi[k] = 0;
+    }
+    packed_rows = 0;
+  };
+
+  for (int64_t base = w_begin; base < w_end; base += 64) {
+    const int64_t r = base + lane;
+    const int lab = (r < w_end) ? a.y[r] : -1;
+    if (r < w_end && (lab < 0 || lab >= a.C)) bad_label = true;
+    uint64_t mask = __ballot(lab == cls);
+    matched += __popcll(mask);
+    while (mask) {
+      int64_t rows[kBatch];
+      int cnt = 0;
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        if (mask) {
+          const int idx = __ffsll((unsigned long long)mask) - 1;
+          mask &= mask - 1;
+          rows[k] = base + idx;
+          ++cnt;
+        } else {
+          rows[k] = -1;
+        }
+      }
+      dev::u32x4 v[kBatch][NV];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[k][q] = dev::u32x4{0u, 0u, 0u, 0u};
+        if (rows[k] >= 0) {
+          const int64_t row_off = rows[k] * a.ld_bytes;
+          const uint8_t* p = a.x + row_off + col;
+          if (row_off + chunk_end <= a.total_bytes) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[k][q] = dev::load16(p + 16 * q);
+          } else {
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+              v[k][q] = dev::load16_guarded(p + 16 * q, a.total_bytes - (row_off + col + 16 * q));
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        if (XT == NB_X_I32) {
+#pragma unroll
+          for (int q = 0; q < NV; ++q) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              const int e = 4 * q + d;
+              const int32_t val = (int32_t)v[k][q][d];
+              const bool valid = (f0 + e) < a.F;
+              if (valid && val < 0) negative = true;
+              if (valid) acc[e] += BIN ? (int64_t)(val > 0) : (int64_t)val;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const uint32_t w = v[k][0][d];
+            uint32_t l = w & 0x00FF00FFu, h = (w >> 8) & 0x00FF00FFu;
+            if (BIN) {   // presence: (b + 255) has bit 8 set iff b >= 1
+              l = ((l + 0x00FF00FFu) >> 8) & 0x00010001u;
+              h = ((h + 0x00FF00FFu) >> 8) & 0x00010001u;
+            }
+            lo[d] += l;
+            hi[d] += h;
+          }
+        }
+      }
+      if (XT != NB_X_I32) {
+        packed_rows += cnt;
+        if (packed_rows > 256 - kBatch) flush();
+      }
+    }
+  }
+  if (XT != NB_X_I32) flush();
+
+  if (bad_label && cls == 0 && ch == 0) atomicOr(&a.status[kStatusFlags], kFlagBadLabel);
+  if (negative) atomicOr(&a.status[kStatusFlags], kFlagNegative);
+
+  // combine the four waves in LDS, then one partial row per workgroup
+  __shared__ int64_t red[kWaves - 1][kSeg][64];
+  __shared__ int64_t red_m[kWaves];
+  if (wave > 0) {
+#pragma unroll
+    for (int e = 0; e < kSeg; ++e) red[wave - 1][e][lane] = acc[e];
+  }
+  if (lane == 0) red_m[wave] = matched;
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int w = 0; w < kWaves - 1; ++w)
+#pragma unroll
+      for (int e = 0; e < kSeg; ++e) acc[e] += red[w][e][lane];
+    int64_t* dst = a.part + ((int64_t)slot * a.C + cls) * a.Fp + f0;
+#pragma unroll
+    for (int e = 0; e < kSeg; ++e) dst[e] = acc[e];
+    if (ch == 0 && lane == 0)
+      a.nc_part[(int64_t)slot * a.C + cls] = red_m[0] + red_m[1] + red_m[2] + red_m[3];
+  }
+}
+
+__global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__ part,
+                                                    const int64_t* __restrict__ nc_part, int S, int C,
+                                                    int F, int Fp, int32_t* __restrict__ counts,
+                                                    int64_t* __restrict__ class_totals,
+                                                    int32_t* __restrict__ status) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f < F) {
+    int64_t s = 0;
+    for (int k = 0; k < S; ++k) s += part[((int64_t)k * C + c) * Fp + f];
+    if (s > INT32_MAX) {
+      atomicOr(&status[kStatusFlags], kFlagOverflow);
+      s = INT32_MAX;
+    }
+    counts[(int64_t)c * F + f] = (int32_t)s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int64_t m = 0;
+    for (int k = 0; k < S; ++k) m += nc_part[(int64_t)k * C + c];
+    class_totals[c] = m;
+  }
+}
+
+struct TableArgs {
+  const int32_t* counts;
+  const int64_t* class_totals;
+  int64_t* class_sums;
+  double* log_theta;
+  double* log_1m_theta;
+  double* weight;
+  double* bias;
+  int32_t* status;
+  double alpha;
+  int32_t F, C, kind, min_files;
+};
+
+// One workgroup per class.
+__global__ __launch_bounds__(256) void class_tables(TableArgs a) {
+  const int c = blockIdx.x;
+  const int t = threadIdx.x;
+  __shared__ int64_t si[256];
+  __shared__ double sd[256];
+  const int32_t* T = a.counts + (int64_t)c * a.F;
+
+  int64_t s = 0;
+  for (int f = t; f < a.F; f += 256) s += T[f];
+  si[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) si[t] += si[t + w];
+    __syncthreads();
+  }
+  const int64_t Sc = si[0];
+  const int64_t Nc = a.class_totals[c];
+  int64_t N = 0;
+  for (int k = 0; k < a.C; ++k) N += a.class_totals[k];
+  if (t == 0) {
+    a.class_sums[c] = (a.kind == NB_MULTINOMIAL) ? Sc : Nc;
+    if (Nc < a.min_files || Nc < 1) atomicOr(&a.status[kStatusFlags], kFlagMinFiles);
+  }
+
+  const double al = a.alpha;
+  double part = 0.0;
+  if (a.kind == NB_MULTINOMIAL) {
+    const double den = log((double)Sc + al * (double)a.F);
+    for (int f = t; f < a.F; f += 256) {
+      const double lt = log((double)T[f] + al) - den;
+      const int64_t i = (int64_t)c * a.F + f;
+      a.log_theta[i] = lt;
+      a.log_1m_theta[i] = 0.0;
+      a.weight[i] = lt;
+    }
+  } else {
+    const double den = log((double)Nc + 2.0 * al);
+    for (int f = t; f < a.F; f += 256) {
+      const double lt = log((double)T[f] + al) - den;
+      const double l1 = log((double)(Nc - T[f]) + al) - den;
+      const int64_t i = (int64_t)c * a.F + f;
+      a.log_theta[i] = lt;
+      a.log_1m_theta[i] = l1;
+      a.weight[i] = lt - l1;
+      part += l1;
+    }
+  }
+  sd[t] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sd[t] += sd[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double lp = log((double)Nc) - log((double)N);
+    a.bias[c] = (a.kind == NB_MULTINOMIAL) ? lp : lp + sd[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void form_rows(const double* __restrict__ W, const double* __restrict__ bias,
+                                                int C, int F, int Fp, float* __restrict__ rows32,
+                                                uint16_t* __restrict__ rows16, float* __restrict__ row_bias,
+                                                int32_t* __restrict__ status) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  const int P = (C == 2) ? 1 : C;
+  if (f < Fp) {
+    if (f >= F) {
+      for (int r = 0; r <= P; ++r) {
+        rows32[(int64_t)r * Fp + f] = 0.0f;
+        rows16[(int64_t)r * Fp + f] = 0;
+      }
+    } else if (C == 2) {
+      const double w0 = W[f], w1 = W[(int64_t)F + f];
+      const double d = w1 - w0;
+      rows32[f] = (float)d;
+      rows16[f] = dev::f64_to_bf16_rne(d);
+      rows32[(int64_t)Fp + f] = (float)w0;
+      rows16[(int64_t)Fp + f] = dev::f64_to_bf16_rne(w0);
+    } else {
+      double m = 0.0;
+      for (int c = 0; c < C; ++c) m += W[(int64_t)c * F + f];
+      m /= (double)C;
+      for (int c = 0; c < C; ++c) {
+        const double v = W[(int64_t)c * F + f] - m;
+        rows32[(int64_t)c * Fp + f] = (float)v;
+        rows16[(int64_t)c * Fp + f] = dev::f64_to_bf16_rne(v);
+      }
+      rows32[(int64_t)C * Fp + f] = (float)m;
+      rows16[(int64_t)C * Fp + f] = dev::f64_to_bf16_rne(m);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (C == 2) {
+      row_bias[0] = (float)(bias[1] - bias[0]);
+      row_bias[1] = (float)bias[0];
+    } else {
+      double mb = 0.0;
+      for (int c = 0; c < C; ++c) mb += bias[c];
+      mb /= (double)C;
+      for (int c = 0; c < C; ++c) row_bias[c] = (float)(bias[c] - mb);
+      row_bias[C] = (float)mb;
+    }
+    status[kStatusTrained] = (status[kStatusFlags] == 0) ? 1 : 0;
+  }
+}
+
+int64_t train_slots(int32_t C, int32_t F, int64_t n) {
+  const int64_t nch = (align_up((size_t)F, kFeaturePad)) / kChunk;
+  int64_t s = (kTargetUnits + C * nch - 1) / (C * nch);
+  const int64_t by_rows = std::max<int64_t>(1, (n + kMinRowsPerSlot - 1) / kMinRowsPerSlot);
+  return std::max<int64_t>(1, std::min(s, by_rows));
+}
+
+int flags_to_status(int32_t flags) {
+  if (flags & (kFlagBadLabel | kFlagNegative))
+    return fail(NB_EDATA, (flags & kFlagBadLabel) ? "a label is outside [0, C)" : "a feature value is negative");
+  if (flags & kFlagOverflow) return fail(NB_EOVERFLOW, "a per-class count exceeds INT32_MAX");
+  if (flags & kFlagMinFiles) return fail(NB_EMINFILES, "a class has fewer training files than required");
+  return NB_OK;
+}
+
+}  // namespace
+}  // namespace nb
+
+using namespace nb;
+
+extern "C" {
+
+size_t nb_train_workspace_bytes(int32_t n_classes, int32_t n_features, int64_t n, int32_t xtype) {
+  nb_layout L;
+  if (!compute_layout(n_classes, n_features, &L) || n < 0 || elem_bytes(xtype) == 0) return 0;
+  const int64_t S = train_slots(n_classes, n_features, n);
+  return align_up((size_t)S * n_classes * L.padded_features * 8, kAlign) +
+         align_up((size_t)S * n_classes * 8, kAlign);
+}
+
+int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, const int32_t* y,
+             double alpha, int32_t min_files_per_class, void* workspace, size_t workspace_bytes,
+             int32_t flags, void* stream) {
+  nb_layout L;
+  int rc = check_model(m, &L);
+  if (rc) return rc;
+  m->trained = 0;
+  const int C = m->n_classes, F = m->n_features;
+  if (xtype != NB_X_U8 && xtype != NB_X_I32)
+    return fail(NB_EINVAL, "training features must be NB_X_U8 or NB_X_I32");
+  if (n < 1) return fail(NB_EINVAL, "n must be >= 1");
+  if (ld < F) return fail(NB_EINVAL, "ld must be >= n_features");
+  const int eb = elem_bytes(xtype);
+  if (((int64_t)ld * eb) % 4 != 0) return fail(NB_EINVAL, "row stride must be a multiple of 4 bytes");
+  if (!x || !y) return fail(NB_EINVAL, "x and y must be non-NULL");
+  if ((reinterpret_cast<uintptr_t>(x) & 3) != 0) return fail(NB_EINVAL, "x must be 4-byte aligned");
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(NB_EINVAL, "alpha must be finite and > 0");
+  if (min_files_per_class < 1) return fail(NB_EINVAL, "min_files_per_class must be >= 1");
+  if (xtype == NB_X_U8 && n > INT32_MAX / 255)
+    return fail(NB_EOVERFLOW, "n * 255 exceeds INT32_MAX: byte counts could overflow int32");
+  const size_t need = nb_train_workspace_bytes(C, F, n, xtype);
+  if (!workspace || workspace_bytes < need)
+    return fail(NB_ENOMEM, "workspace smaller than nb_train_workspace_bytes()");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0) return fail(NB_EINVAL, "workspace must be 8-byte aligned");
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint8_t* base = static_cast<uint8_t*>(m->dev);
+  int32_t* status = reinterpret_cast<int32_t*>(base + L.off_status);
+  const int Fp = L.padded_features;
+  const int64_t S = train_slots(C, F, n);
+  int64_t* part = static_cast<int64_t*>(workspace);
+  int64_t* nc_part = reinterpret_cast<int64_t*>(static_cast<uint8_t*>(workspace) +
+                                                align_up((size_t)S * C * Fp * 8, kAlign));
+
+  hipLaunchKernelGGL(init_status, dim3(1), dim3(64), 0, s, status);
+  NB_HIP_CHECK(hipGetLastError());
+
+  CountArgs ca;
+  ca.x = static_cast<const uint8_t*>(x);
+  ca.ld_bytes = ld * eb;
+  ca.n = n;
+  ca.total_bytes = ((n - 1) * ld + F) * (int64_t)eb;
+  ca.y = y;
+  ca.rows_per_slot = (n + S - 1) / S;
+  ca.part = part;
+  ca.nc_part = nc_part;
+  ca.status = status;
+  ca.F = F;
+  ca.C = C;
+  ca.Fp = Fp;
+  const dim3 grid((unsigned)S, (unsigned)C, (unsigned)(Fp / kChunk));
+  const bool bin = (m->kind == NB_BERNOULLI);
+  if (xtype == NB_X_U8) {
+    if (bin) hipLaunchKernelGGL((count_kernel<NB_X_U8, true>), grid, dim3(kThreads), 0, s, ca);
+    else hipLaunchKernelGGL((count_kernel<NB_X_U8, false>), grid, dim3(kThreads), 0, s, ca);
+  } else {
+    if (bin) hipLaunchKernelGGL((count_kernel<NB_X_I32, true>), grid, dim3(kThreads), 0, s, ca);
+    else hipLaunchKernelGGL((count_kernel<NB_X_I32, false>), grid, dim3(kThreads), 0, s, ca);
+  }
+  NB_HIP_CHECK(hipGetLastError());
+
+  hipLaunchKernelGGL(reduce_counts, dim3((unsigned)((F + 255) / 256), (unsigned)C), dim3(256), 0, s, part,
+                     nc_part, (int)S, C, F, Fp, reinterpret_cast<int32_t*>(base + L.off_counts),
+                     reinterpret_cast<int64_t*>(base + L.off_class_totals), status);
+  NB_HIP_CHECK(hipGetLastError());
+
+  TableArgs ta;
+  ta.counts = reinterpret_cast<const int32_t*>(base + L.off_counts);
+  ta.class_totals = reinterpret_cast<const int64_t*>(base + L.off_class_totals);
+  ta.class_sums = reinterpret_cast<int64_t*>(base + L.off_class_sums);
+  ta.log_theta = reinterpret_cast<double*>(base + L.off_log_theta);
+  ta.log_1m_theta = reinterpret_cast<double*>(base + L.off_log_1m_theta);
+  ta.weight = reinterpret_cast<double*>(base + L.off_weight);
+  ta.bias = reinterpret_cast<double*>(base + L.off_bias);
+  ta.status = status;
+  ta.alpha = alpha;
+  ta.F = F;
+  ta.C = C;
+  ta.kind = m->kind;
+  ta.min_files = min_files_per_class;
+  hipLaunchKernelGGL(class_tables, dim3((unsigned)C), dim3(256), 0, s, ta);
+  NB_HIP_CHECK(hipGetLastError());
+
+  hipLaunchKernelGGL(form_rows, dim3((unsigned)(Fp / 256)), dim3(256), 0, s, ta.weight, ta.bias, C, F, Fp,
+                     reinterpret_cast<float*>(base + L.off_form_f32),
+                     reinterpret_cast<uint16_t*>(base + L.off_form_bf16),
+                     reinterpret_cast<float*>(base + L.off_form_bias), status);
+  NB_HIP_CHECK(hipGetLastError());
+
+  if (flags & NB_TRAIN_ASYNC) return NB_OK;
+  return nb_model_status(m, stream);
+}
+
+int nb_model_status(nb_model* m, void* stream) {
+  nb_layout L;
+  int rc = check_model(m, &L);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int32_t st[4] = {0, 0, 0, 0};
+  NB_HIP_CHECK(hipMemcpyAsync(st, static_cast<uint8_t*>(m->dev) + L.off_status, sizeof(st),
+                              hipMemcpyDeviceToHost, s));
+  NB_HIP_CHECK(hipStreamSynchronize(s));
+  m->trained = st[kStatusTrained];
+  return flags_to_status(st[kStatusFlags]);
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+"""The C ABI library on the CPU: it loads, exports every symbol include/nb.h
+declares, computes layouts, validates arguments before touching a device, and
+its host-side size-group routing matches the oracle.  No compute call runs."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1905_13746_amd as nbg
+from paper_1905_13746_amd import _lib
+from oracle import groups
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nb.h")
+
+FAKE_DEV = 0x7F0000000000   # 256-byte aligned; never dereferenced by these tests
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nb_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return nbg.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+
+
+def test_version_and_layout(lib):
+    assert b"gfx950" in lib.nb_version()
+    L = _lib.NbLayout()
+    assert lib.nb_model_layout(2, 1000, ctypes.byref(L)) == 0
+    assert L.padded_features == 1024 and L.form_rows == 1
+    offs = [L.off_status, L.off_class_totals, L.off_class_sums, L.off_counts, L.off_log_theta,
+            L.off_log_1m_theta, L.off_weight, L.off_bias, L.off_form_f32, L.off_form_bf16, L.off_form_bias]
+    assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
+    assert L.off_counts - L.off_class_sums >= 16 and L.off_log_theta - L.off_counts >= 4 * 2000
+    assert L.total_bytes == lib.nb_model_bytes(2, 1000)
+    assert lib.nb_model_layout(16, 4096, ctypes.byref(L)) == 0 and L.form_rows == 16
+    assert lib.nb_model_bytes(1, 10) == 0 and lib.nb_model_bytes(257, 10) == 0
+    assert lib.nb_model_bytes(2, 0) == 0
+    assert lib.nb_model_layout(1, 10, ctypes.byref(L)) == -1
+
+
+def _model(C=2, F=100, kind=0):
+    return _lib.NbModel(kind, C, F, 0, FAKE_DEV)
+
+
+def _train(lib, m, **kw):
+    a = dict(x=FAKE_DEV, xtype=0, n=10, ld=m.n_features, y=FAKE_DEV, alpha=1.0, minf=1,
+             ws=FAKE_DEV, wsb=1 << 30, flags=0)
+    a.update(kw)
+    return lib.nb_train(ctypes.byref(m), a["x"], a["xtype"], a["n"], a["ld"], a["y"], a["alpha"], a["minf"],
+                        a["ws"], a["wsb"], a["flags"], None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(alpha=0.0), -1), (dict(alpha=float("nan")), -1), (dict(n=0), -1),
+    (dict(ld=50), -1), (dict(xtype=2), -1), (dict(xtype=9), -1), (dict(x=None), -1),
+    (dict(y=None), -1), (dict(minf=0), -1), (dict(wsb=16), -6), (dict(ws=None), -6),
+    (dict(x=FAKE_DEV + 2), -1), (dict(n=9_000_000), -2),
+])
+def test_train_argument_errors(lib, kw, code):
+    assert _train(lib, _model(), **kw) == code
+    assert lib.nb_last_error()
+
+
+def test_train_rejects_bad_models(lib):
+    assert _train(lib, _model(C=1)) == -1
+    assert _train(lib, _model(kind=5)) == -1
+    bad = _lib.NbModel(0, 2, 100, 0, FAKE_DEV + 8)
+    assert _train(lib, bad) == -1
+    assert lib.nb_train(None, FAKE_DEV, 0, 10, 100, FAKE_DEV, 1.0, 1, FAKE_DEV, 1 << 30, 0, None) == -1
+
+
+def _score(lib, m, **kw):
+    a = dict(x=FAKE_DEV, xtype=0, n=10, ld=m.n_features, wt=0, lab=FAKE_DEV, lp=FAKE_DEV, sc=None)
+    a.update(kw)
+    return lib.nb_score(ctypes.byref(m), a["x"], a["xtype"], a["n"], a["ld"], a["wt"], a["lab"], a["lp"],
+                        a["sc"], None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(xtype=7), -1), (dict(wt=3), -1), (dict(n=-1), -1), (dict(lab=None, lp=None), -1),
+    (dict(x=None), -1), (dict(ld=99), -1), (dict(ld=101), -1), (dict(lp=FAKE_DEV + 4), -1),
+])
+def test_score_argument_errors(lib, kw, code):
+    assert _score(lib, _model(), **kw) == code
+
+
+def test_score_empty_batch_is_noop(lib):
+    assert _score(lib, _model(), n=0, x=None) == 0
+
+
+def test_workspace_size_is_deterministic(lib):
+    a = lib.nb_train_workspace_bytes(2, 1000, 200_000, 0)
+    assert a > 0 and a == lib.nb_train_workspace_bytes(2, 1000, 200_000, 0)
+    assert lib.nb_train_workspace_bytes(1, 1000, 10, 0) == 0
+
+
+def test_route_groups_matches_oracle(lib):
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        G, C = int(rng.integers(1, 30)), int(rng.integers(2, 4))
+        cc = rng.integers(0, 12, size=(G, C))
+        trained = groups.trained_mask(cc, 6)
+        if not trained.any():
+            with pytest.raises(nbg.NBError):
+                nbg.route_groups(cc, 6)
+            continue
+        assert (nbg.route_groups(cc, 6) == groups.route(trained)).all()
+
+
+def test_route_groups_paper_fixture():
+    import json
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "size_groups.json")))
+    cc = np.full((g["n_groups"], 2), 40)
+    for k, grp in enumerate(g["untrained_1based"]):
+        cc[grp - 1, k % 2] = 3
+    r = nbg.route_groups(cc, g["min_files"])
+    for grp_s, tgt in g["fallback_1based"].items():
+        assert r[int(grp_s) - 1] + 1 == tgt

@@ -34,6 +34,27 @@ __device__ __forceinline__ u32x4 load16_guarded(const uint8_t* p, int64_t avail)
   return out;
 }
 
+// Raw buffer resource over [base, base + bytes): loads at offsets beyond
+// `bytes` return zero instead of touching memory.  Word 3 is the gfx9-family
+// descriptor format for untyped dword access.
+// `bytes` must be >= 0; it is capped at 2^31 - 1 (the descriptor field).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const uint64_t b = (uint64_t)bytes;
+  const int32_t n = (b >> 31) ? 0x7FFFFFFF : (int32_t)b;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
+}
+
+// Cache policy of the streaming feature loads (gfx940+ bits: 1 sc0, 2 nt,
+// 16 sc1); non-temporal by default: each feature byte is read once.
+#ifndef NB_STREAM_CPOL
+#define NB_STREAM_CPOL 2
+#endif
+
+__device__ __forceinline__ u32x4 buffer_load16(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, NB_STREAM_CPOL);
+  return u32x4{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};
+}
+
 // Round-to-nearest-even of an FP64 value to BF16, in one rounding: add the
 // rounding increment below bit 45 of the FP64 significand (ties to even),
 // truncate, and take the (then exact) FP32 image's upper half.  Valid for the

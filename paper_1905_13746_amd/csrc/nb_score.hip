@@ -38,7 +38,16 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kRowSteps = 8;
+// Rows per lane group per block, and whether a wave double-buffers its loads
+// (the next unit's loads in flight while the current one is accumulated).
+#ifndef NB_ROW_STEPS
+#define NB_ROW_STEPS 8
+#endif
+#ifndef NB_PIPELINE
+#define NB_PIPELINE 1
+#endif
+constexpr int kRowSteps = NB_ROW_STEPS;
+constexpr bool kPipeline = NB_PIPELINE != 0;
 
 struct Score2Args {
   const uint8_t* x;
@@ -51,6 +60,7 @@ struct Score2Args {
   int32_t* labels;
   float* log_post;
   float* scores;
+  int64_t nfast;            // leading blocks with every row present and in bounds
   int32_t F, Fp, nch, wt;
 };
 
@@ -102,7 +112,140 @@ __device__ __forceinline__ void accumulate_seg(const dev::u32x4 (&v)[(XT == NB_X
   }
 }
 
-template <int XT, int LPR, int NS, bool BIN>
+// Destination of outputs the caller did not request: the fast path stores
+// every output unconditionally so the number of memory operations in flight
+// is known at compile time (loads of the next unit stay in flight).
+__device__ int32_t g_sink_label[64];
+__device__ float2 g_sink_pair[64];
+
+// Reduce acc[R][NS] across the LPR lanes of each row group (transposed
+// butterfly), stage the per-row totals in LDS and run the fused epilogue for
+// the block's rows [row0, row0 + nrows).  FAST: nrows == BR and no branches
+// around the stores (lanes beyond BR repeat a row: same value, same address).
+template <int LPR, int NS, bool FAST>
+__device__ __forceinline__ void finish_block(const Score2Args& a, float (&acc)[kRowSteps][NS], int lane, int wave,
+                                             int sub, const float (&rb)[NS], int64_t row0, int nrows,
+                                             float (*stage)[NS][(64 / LPR) * kRowSteps]) {
+  constexpr int G = 64 / LPR;
+  constexpr int R = kRowSteps;
+  constexpr int BR = G * R;
+  constexpr int V = R * NS;
+  float val[V];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) val[i * NS + s] = acc[i][s];
+  int offset = 0;
+  bool owner = true;
+  int cnt = V;
+#pragma unroll
+  for (int m = LPR / 2; m >= 1; m >>= 1) {
+    const bool up = (lane & m) != 0;
+    if (cnt > 1) {
+      const int h = cnt / 2;
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const float send = up ? val[k] : val[k + h];
+        const float keep = up ? val[k + h] : val[k];
+        val[k] = keep + __shfl_xor(send, m);
+      }
+      if (up) offset += h;
+      cnt = h;
+    } else {
+      val[0] += __shfl_xor(val[0], m);
+      if (up) owner = false;
+    }
+  }
+  // cnt values remain per lane, value indices offset .. offset + cnt - 1
+  if (owner) {
+#pragma unroll
+    for (int k = 0; k < cnt; ++k) {
+      const int idx = offset + k;
+      stage[wave][idx % NS][(idx / NS) * G + sub] = val[k];
+    }
+  }
+  wave_lds_sync();
+  const bool want_lab = a.labels != nullptr, want_lp = a.log_post != nullptr, want_sc = a.scores != nullptr;
+#pragma unroll
+  for (int L0 = 0; L0 < BR; L0 += 64) {
+    const int L = (BR >= 64) ? L0 + lane : lane % BR;
+    if (FAST || L < nrows) {
+      const int64_t row = row0 + L;
+      const float delta = stage[wave][0][L] + rb[0];
+      // log(1 + e^-|delta|) with the hardware exp/log: absolute error ~1e-7
+      const float t = __logf(1.0f + __expf(-fabsf(delta)));
+      float2 lp;
+      lp.x = fminf(-delta, 0.0f) - t;
+      lp.y = fminf(delta, 0.0f) - t;
+      if (FAST) {
+        int32_t* pl = want_lab ? a.labels + row : g_sink_label + lane;
+        float2* pp = want_lp ? reinterpret_cast<float2*>(a.log_post) + row : g_sink_pair + lane;
+        *pl = delta > 0.0f ? 1 : 0;
+        *pp = lp;
+        if (NS == 2) {
+          float2 sc;
+          sc.x = stage[wave][NS - 1][L] + rb[NS - 1];
+          sc.y = sc.x + delta;
+          float2* ps = want_sc ? reinterpret_cast<float2*>(a.scores) + row : g_sink_pair + lane;
+          *ps = sc;
+        }
+      } else {
+        if (want_lab) a.labels[row] = delta > 0.0f ? 1 : 0;
+        if (want_lp) reinterpret_cast<float2*>(a.log_post)[row] = lp;
+        if (NS == 2 && want_sc) {
+          float2 sc;
+          sc.x = stage[wave][NS - 1][L] + rb[NS - 1];
+          sc.y = sc.x + delta;
+          reinterpret_cast<float2*>(a.scores)[row] = sc;
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
+template <int XT, int NS>
+__device__ __forceinline__ void load_table(const float* tbl, int Fp, int fc, float (&w)[NS][16]) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const float4* t4 = reinterpret_cast<const float4*>(tbl + s * Fp + fc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = t4[q];
+      w[s][4 * q + 0] = t.x;
+      w[s][4 * q + 1] = t.y;
+      w[s][4 * q + 2] = t.z;
+      w[s][4 * q + 3] = t.w;
+    }
+  }
+}
+
+// FP8 bytes past the last feature may hold NaN encodings: mask them.
+__device__ __forceinline__ void fp8_keep_mask(int F, int fc, uint32_t (&keep)[4]) {
+  const int nv = max(0, F - fc);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int nb = min(4, max(0, nv - 4 * d));
+    keep[d] = (nb >= 4) ? ~0u : ((1u << (8 * nb)) - 1u);
+  }
+}
+
+template <int XT, int NS, bool BIN, int NV>
+__device__ __forceinline__ void accumulate_rows(dev::u32x4 (&v)[kRowSteps][NV], const float (&w)[NS][16],
+                                                const uint32_t (&keep)[4], bool masked,
+                                                float (&acc)[kRowSteps][NS]) {
+#pragma unroll
+  for (int i = 0; i < kRowSteps; ++i) {
+    if (XT == NB_X_FP8 && masked) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[i][0][d] &= keep[d];
+    }
+    accumulate_seg<XT, NS, BIN>(v[i], w, acc[i]);
+  }
+}
+
+// MULTI: F spans more than one chunk of 16*LPR features (only with LPR = 64).
+template <int XT, int LPR, int NS, bool BIN, bool MULTI>
 __global__ __launch_bounds__(kThreads) void score2_kernel(Score2Args a) {
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
   constexpr int NV = EB;
@@ -110,7 +253,6 @@ __global__ __launch_bounds__(kThreads) void score2_kernel(Score2Args a) {
   constexpr int R = kRowSteps;
   constexpr int BR = G * R;             // rows per block
   constexpr int CW = 16 * LPR;          // features per chunk
-  constexpr int V = R * NS;             // values to reduce per lane
 
   extern __shared__ float tbl[];        // [NS][Fp]
   __shared__ float stage[kWaves][NS][BR];
@@ -119,139 +261,139 @@ __global__ __launch_bounds__(kThreads) void score2_kernel(Score2Args a) {
     tbl[i] = (a.wt == NB_W_BF16) ? dev::bf16_to_f32(a.rows16[i]) : a.rows32[i];
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = lane / LPR, j = lane % LPR;
-  const int64_t nblk = (a.n + BR - 1) / BR;
+  const int64_t wave_id = (int64_t)blockIdx.x * kWaves + wave;
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-  const int64_t span = (int64_t)a.nch * CW * EB;   // bytes of a row a block may touch
+  const int nch = MULTI ? a.nch : 1;
+  const int64_t ld = a.ld_bytes;
+  // this lane's byte offsets inside a block: row (i*G + sub), feature 16*j
+  uint32_t voff[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) voff[i] = (uint32_t)((i * G + sub) * ld) + (uint32_t)(16 * j * EB);
 
   float rb[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) rb[s] = a.row_bias[s];
 
-  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < nblk; blk += nwaves) {
-    const int64_t row0 = blk * BR;
-    const int64_t last = min(row0 + BR, a.n) - 1;
-    const bool safe = last * a.ld_bytes + span <= a.total_bytes;
+  float w[NS][16];
+  uint32_t keep[4] = {~0u, ~0u, ~0u, ~0u};
+  if (!MULTI) {
+    load_table<XT, NS>(tbl, a.Fp, 16 * j, w);
+    if (XT == NB_X_FP8) fp8_keep_mask(a.F, 16 * j, keep);
+  }
 
-    float acc[R][NS];
+  float acc[R][NS];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+
+  // ---- fast blocks [0, nfast): every row present and every load in bounds.
+  // Units (block, chunk) are visited in order; the loads of the next unit are
+  // in flight while the current one is accumulated (two register buffers).
+  // per-wave counters are 32-bit so loop control stays on the scalar unit
+  const int my_blocks = (a.nfast > wave_id) ? (int)((a.nfast - wave_id + nwaves - 1) / nwaves) : 0;
+  const int units = my_blocks * nch;
+  dev::u32x4 buf0[R][NV], buf1[R][NV];
+  int ib = 0;       // index of the block being issued, among this wave's blocks
+  int ich = 0;      // chunk being issued
+  auto rewind = [&]() {          // point the issue cursor back at the last issued unit
+    if (ich == 0) {
+      ich = nch - 1;
+      --ib;
+    } else {
+      --ich;
+    }
+  };
+  auto issue = [&](dev::u32x4 (&dst)[R][NV]) {
+    const int64_t blk = wave_id + (int64_t)ib * nwaves;
+    const int64_t off = blk * BR * ld + (int64_t)ich * CW * EB;
+    const auto rsrc = dev::make_rsrc(a.x + off, a.total_bytes - off);
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+      for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, voff[i] + 16 * q);
+    // keep the loads here: the scheduler would otherwise sink them into the
+    // arithmetic of the unit being consumed and shrink the overlap
+    __builtin_amdgcn_sched_barrier(0);
+    if (++ich == nch) {
+      ich = 0;
+      ++ib;
+    }
+  };
+  int cb = 0;       // block being computed
+  int cch = 0;      // chunk being computed
+  auto consume = [&](dev::u32x4 (&src)[R][NV]) {
+    if (MULTI) {
+      const int fc = cch * CW + 16 * j;
+      load_table<XT, NS>(tbl, a.Fp, fc, w);
+      if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
+    }
+    accumulate_rows<XT, NS, BIN, NV>(src, w, keep, true, acc);
+    if (++cch == nch) {
+      finish_block<LPR, NS, true>(a, acc, lane, wave, sub, rb, (wave_id + (int64_t)cb * nwaves) * BR, BR, stage);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+      cch = 0;
+      ++cb;
+    }
+  };
+  // The prefetch of the unit after the last one re-reads the last unit (an L2
+  // hit) so that every iteration issues the same loads unconditionally.
+  if (units > 0 && !kPipeline) {
+    for (int u = 0; u < units; ++u) {
+      issue(buf0);
+      consume(buf0);
+    }
+  } else if (units > 0) {
+    issue(buf0);
+    for (int u = 0;; u += 2) {
+      if (u + 1 >= units) rewind();
+      issue(buf1);
+      consume(buf0);
+      if (u + 1 >= units) break;
+      if (u + 2 >= units) rewind();
+      issue(buf0);
+      consume(buf1);
+      if (u + 2 >= units) break;
+    }
+  }
 
-    for (int ch = 0; ch < a.nch; ++ch) {
+  // ---- remaining blocks [nfast, nblk): guarded loads, partial rows
+  const int64_t nblk = (a.n + BR - 1) / BR;
+  for (int64_t blk = a.nfast + wave_id; blk < nblk; blk += nwaves) {
+    const int64_t row0 = blk * BR;
+    const int nrows = (int)min((int64_t)BR, a.n - row0);
+    for (int ch = 0; ch < nch; ++ch) {
       const int fc = ch * CW + 16 * j;
-      float w[NS][16];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const float4* t4 = reinterpret_cast<const float4*>(tbl + s * a.Fp + fc);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 t = t4[q];
-          w[s][4 * q + 0] = t.x;
-          w[s][4 * q + 1] = t.y;
-          w[s][4 * q + 2] = t.z;
-          w[s][4 * q + 3] = t.w;
-        }
-      }
-      // FP8 bytes past the last feature may hold NaN encodings: clear them
-      uint32_t keep[4] = {~0u, ~0u, ~0u, ~0u};
-      if (XT == NB_X_FP8 && fc + 16 > a.F) {
-        const int nv = max(0, a.F - fc);
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          const int nb = min(4, max(0, nv - 4 * d));
-          keep[d] = (nb >= 4) ? ~0u : ((1u << (8 * nb)) - 1u);
-        }
+      if (MULTI) {
+        load_table<XT, NS>(tbl, a.Fp, fc, w);
+        if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
       }
       dev::u32x4 v[R][NV];
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        const int64_t row = row0 + i * G + sub;
+        const int L = i * G + sub;
 #pragma unroll
         for (int q = 0; q < NV; ++q) v[i][q] = dev::u32x4{0u, 0u, 0u, 0u};
-        if (row < a.n) {
-          const int64_t off = row * a.ld_bytes + (int64_t)fc * EB;
-          const uint8_t* p = a.x + off;
-          if (safe) {
+        if (L < nrows) {
+          const int64_t off = (row0 + L) * ld + (int64_t)fc * EB;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) v[i][q] = dev::load16(p + 16 * q);
-          } else {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) v[i][q] = dev::load16_guarded(p + 16 * q, a.total_bytes - off - 16 * q);
-          }
+          for (int q = 0; q < NV; ++q)
+            v[i][q] = dev::load16_guarded(a.x + off + 16 * q, a.total_bytes - off - 16 * q);
         }
       }
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        if (XT == NB_X_FP8) {
-#pragma unroll
-          for (int d = 0; d < 4; ++d) v[i][0][d] &= keep[d];
-        }
-        accumulate_seg<XT, NS, BIN>(v[i], w, acc[i]);
-      }
+      accumulate_rows<XT, NS, BIN, NV>(v, w, keep, true, acc);
     }
-
-    // transposed butterfly over the LPR lanes of each row group
-    float val[V];
+    finish_block<LPR, NS, false>(a, acc, lane, wave, sub, rb, row0, nrows, stage);
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) val[i * NS + s] = acc[i][s];
-    int offset = 0;
-    bool owner = true;
-    {
-      int cnt = V;
-#pragma unroll
-      for (int m = LPR / 2; m >= 1; m >>= 1) {
-        const bool up = (lane & m) != 0;
-        if (cnt > 1) {
-          const int h = cnt / 2;
-#pragma unroll
-          for (int k = 0; k < h; ++k) {
-            const float send = up ? val[k] : val[k + h];
-            const float keep = up ? val[k + h] : val[k];
-            val[k] = keep + __shfl_xor(send, m);
-          }
-          if (up) offset += h;
-          cnt = h;
-        } else {
-          val[0] += __shfl_xor(val[0], m);
-          if (up) owner = false;
-        }
-      }
-      // cnt values remain per lane: indices offset .. offset+cnt-1
-      if (owner) {
-#pragma unroll
-        for (int k = 0; k < cnt; ++k) {
-          const int idx = offset + k;
-          stage[wave][idx % NS][(idx / NS) * G + sub] = val[k];
-        }
-      }
-    }
-    wave_lds_sync();
-    for (int L = lane; L < BR; L += 64) {
-      const int64_t row = row0 + L;
-      if (row < a.n) {
-        const float delta = stage[wave][0][L] + rb[0];
-        const float t = log1pf(expf(-fabsf(delta)));
-        if (a.labels) a.labels[row] = delta > 0.0f ? 1 : 0;
-        if (a.log_post) {
-          float2 lp;
-          lp.x = fminf(-delta, 0.0f) - t;
-          lp.y = fminf(delta, 0.0f) - t;
-          reinterpret_cast<float2*>(a.log_post)[row] = lp;
-        }
-        if (NS == 2 && a.scores) {
-          float2 sc;
-          sc.x = stage[wave][NS - 1][L] + rb[NS - 1];
-          sc.y = sc.x + delta;
-          reinterpret_cast<float2*>(a.scores)[row] = sc;
-        }
-      }
-    }
-    wave_lds_sync();
+      for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
   }
 }
 
@@ -259,27 +401,27 @@ __global__ __launch_bounds__(kThreads) void score2_kernel(Score2Args a) {
 using KernelFn = void (*)(Score2Args);
 
 template <int XT, int NS, bool BIN>
-KernelFn pick_lpr(int lpr) {
+KernelFn pick_lpr(int lpr, bool multi) {
   switch (lpr) {
-    case 4: return score2_kernel<XT, 4, NS, BIN>;
-    case 8: return score2_kernel<XT, 8, NS, BIN>;
-    case 16: return score2_kernel<XT, 16, NS, BIN>;
-    case 32: return score2_kernel<XT, 32, NS, BIN>;
-    default: return score2_kernel<XT, 64, NS, BIN>;
+    case 4: return score2_kernel<XT, 4, NS, BIN, false>;
+    case 8: return score2_kernel<XT, 8, NS, BIN, false>;
+    case 16: return score2_kernel<XT, 16, NS, BIN, false>;
+    case 32: return score2_kernel<XT, 32, NS, BIN, false>;
+    default: return multi ? score2_kernel<XT, 64, NS, BIN, true> : score2_kernel<XT, 64, NS, BIN, false>;
   }
 }
 
 template <int XT>
-KernelFn pick2(int lpr, int ns, bool bin) {
-  if (ns == 1) return bin ? pick_lpr<XT, 1, true>(lpr) : pick_lpr<XT, 1, false>(lpr);
-  return bin ? pick_lpr<XT, 2, true>(lpr) : pick_lpr<XT, 2, false>(lpr);
+KernelFn pick2(int lpr, bool multi, int ns, bool bin) {
+  if (ns == 1) return bin ? pick_lpr<XT, 1, true>(lpr, multi) : pick_lpr<XT, 1, false>(lpr, multi);
+  return bin ? pick_lpr<XT, 2, true>(lpr, multi) : pick_lpr<XT, 2, false>(lpr, multi);
 }
 
-KernelFn pick_score2(int xtype, int lpr, int ns, bool bin) {
+KernelFn pick_score2(int xtype, int lpr, bool multi, int ns, bool bin) {
   switch (xtype) {
-    case NB_X_U8: return pick2<NB_X_U8>(lpr, ns, bin);
-    case NB_X_I32: return pick2<NB_X_I32>(lpr, ns, bin);
-    default: return pick2<NB_X_FP8>(lpr, ns, bin);
+    case NB_X_U8: return pick2<NB_X_U8>(lpr, multi, ns, bin);
+    case NB_X_I32: return pick2<NB_X_I32>(lpr, multi, ns, bin);
+    default: return pick2<NB_X_FP8>(lpr, multi, ns, bin);
   }
 }
 
@@ -333,10 +475,19 @@ int launch_score2(const nb_model* m, const nb_layout& L, const void* x, int32_t 
   a.Fp = L.padded_features;
   a.nch = nch;
   a.wt = wtype;
-  KernelFn fn = pick_score2(xtype, lpr, ns, m->kind == NB_BERNOULLI);
+  const int64_t rows_per_blk = (int64_t)(64 / lpr) * kRowSteps;
+  if (rows_per_blk * a.ld_bytes >= (int64_t)1 << 31)
+    return fail(NB_EINVAL, "row stride too large (a block of rows must span < 2 GiB)");
+  // leading blocks whose rows all exist and whose loads stay inside the buffer
+  {
+    const int64_t span = (int64_t)nch * cw * eb;
+    const int64_t full = n / rows_per_blk;
+    const int64_t rmax = (a.total_bytes >= span) ? (a.total_bytes - span) / a.ld_bytes : -1;
+    a.nfast = std::max<int64_t>(0, std::min(full, (rmax + 1) / rows_per_blk));
+  }
+  KernelFn fn = pick_score2(xtype, lpr, nch > 1, ns, m->kind == NB_BERNOULLI);
   if (lds > 64 * 1024) NB_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int64_t rows_per_blk = (int64_t)(64 / lpr) * kRowSteps;
   const int64_t nblk = (n + rows_per_blk - 1) / rows_per_blk;
   const int64_t want = (nblk + kWaves - 1) / kWaves;
   const int64_t cap = (int64_t)resident_per_cu(reinterpret_cast<const void*>(fn), lds) * device_cu_count();

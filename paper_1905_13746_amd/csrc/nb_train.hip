@@ -19,9 +19,11 @@
 //                 lanes (two features per 32-bit add), flushed to 32-bit every
 //                 <= 256 rows; four waves then combine in LDS and write one
 //                 int64 partial per (slot, class, feature) to the workspace.
-//   reduce_counts sum the partials (integer sums: exact, order-free), check
-//                 the int32 range, write T/D and N_c.
-//   class_tables  one workgroup per class: S_c, the FP64 log theta /
+//   reduce_counts first level of the partial sums, spread over
+//                 (feature group, class, slot group) workgroups.
+//   class_tables  one workgroup per class: the last level of the sums
+//                 (integer: exact and order-free), the int32 range check,
+//                 T/D, N_c, S_c, then the FP64 log theta /
 //                 log(1 - theta) / weights and the bias, with a fixed-order
 //                 tree reduction (deterministic).
 //   form_rows     the scoring rows (log-odds / class-centred + aux) in FP64,
@@ -129,8 +131,10 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
           const int64_t row_off = rows[k] * a.ld_bytes;
           const uint8_t* p = a.x + row_off + col;
           if (row_off + chunk_end <= a.total_bytes) {
+            // streaming, non-temporal loads through a per-row buffer resource
+            const auto rsrc = dev::make_rsrc(a.x + row_off, a.total_bytes - row_off);
 #pragma unroll
-            for (int q = 0; q < NV; ++q) v[k][q] = dev::load16(p + 16 * q);
+            for (int q = 0; q < NV; ++q) v[k][q] = dev::buffer_load16(rsrc, (uint32_t)col + 16 * q);
           } else {
 #pragma unroll
             for (int q = 0; q < NV; ++q)
@@ -199,32 +203,42 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   }
 }
 
+// First-level reduction of the per-slot partials: grid (ceil(F/64), C, RS),
+// 4 slot lanes x 64 features per workgroup; writes RS second-level partials.
+constexpr int kReduceSplit = 8;
+
 __global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__ part,
                                                     const int64_t* __restrict__ nc_part, int S, int C,
-                                                    int F, int Fp, int32_t* __restrict__ counts,
-                                                    int64_t* __restrict__ class_totals,
-                                                    int32_t* __restrict__ status) {
-  const int c = blockIdx.y;
-  const int f = blockIdx.x * 256 + threadIdx.x;
+                                                    int F, int Fp, int64_t* __restrict__ part2,
+                                                    int64_t* __restrict__ nc2) {
+  const int c = blockIdx.y, rs = blockIdx.z, RS = gridDim.z;
+  const int fl = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int f = blockIdx.x * 64 + fl;
+  int64_t s = 0, m = 0;
+  const int stride = 4 * RS;
   if (f < F) {
-    int64_t s = 0;
-    for (int k = 0; k < S; ++k) s += part[((int64_t)k * C + c) * Fp + f];
-    if (s > INT32_MAX) {
-      atomicOr(&status[kStatusFlags], kFlagOverflow);
-      s = INT32_MAX;
-    }
-    counts[(int64_t)c * F + f] = (int32_t)s;
+    int k = rs * 4 + sg;
+#pragma unroll 4
+    for (; k < S; k += stride) s += part[((int64_t)k * C + c) * Fp + f];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    int64_t m = 0;
-    for (int k = 0; k < S; ++k) m += nc_part[(int64_t)k * C + c];
-    class_totals[c] = m;
+  if (blockIdx.x == 0 && fl == 0)
+    for (int k = rs * 4 + sg; k < S; k += stride) m += nc_part[(int64_t)k * C + c];
+  __shared__ int64_t red[4][64];
+  __shared__ int64_t redm[4];
+  red[sg][fl] = s;
+  if (fl == 0) redm[sg] = m;
+  __syncthreads();
+  if (sg == 0) {
+    if (f < F) part2[((int64_t)rs * C + c) * Fp + f] = red[0][fl] + red[1][fl] + red[2][fl] + red[3][fl];
+    if (blockIdx.x == 0 && fl == 0) nc2[(int64_t)rs * C + c] = redm[0] + redm[1] + redm[2] + redm[3];
   }
 }
 
 struct TableArgs {
-  const int32_t* counts;
-  const int64_t* class_totals;
+  const int64_t* part2;    // [RS][C][Fp] second-level partial counts
+  const int64_t* nc2;      // [RS][C]
+  int32_t* counts;
+  int64_t* class_totals;
   int64_t* class_sums;
   double* log_theta;
   double* log_1m_theta;
@@ -232,19 +246,31 @@ struct TableArgs {
   double* bias;
   int32_t* status;
   double alpha;
-  int32_t F, C, kind, min_files;
+  int32_t F, C, Fp, RS, kind, min_files;
 };
 
-// One workgroup per class.
+// One workgroup per class: finish the counts (sum of the second-level
+// partials, int32 range check), S_c, N_c, then the FP64 tables.
 __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
   const int c = blockIdx.x;
   const int t = threadIdx.x;
   __shared__ int64_t si[256];
   __shared__ double sd[256];
-  const int32_t* T = a.counts + (int64_t)c * a.F;
+  int32_t* T = a.counts + (int64_t)c * a.F;
 
   int64_t s = 0;
-  for (int f = t; f < a.F; f += 256) s += T[f];
+  bool over = false;
+  for (int f = t; f < a.F; f += 256) {
+    int64_t v = 0;
+    for (int r = 0; r < a.RS; ++r) v += a.part2[((int64_t)r * a.C + c) * a.Fp + f];
+    if (v > INT32_MAX) {
+      over = true;
+      v = INT32_MAX;
+    }
+    T[f] = (int32_t)v;
+    s += v;
+  }
+  if (over) atomicOr(&a.status[kStatusFlags], kFlagOverflow);
   si[t] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -252,10 +278,16 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
     __syncthreads();
   }
   const int64_t Sc = si[0];
-  const int64_t Nc = a.class_totals[c];
-  int64_t N = 0;
-  for (int k = 0; k < a.C; ++k) N += a.class_totals[k];
+  // N_c of every class (each block needs N = sum_c N_c)
+  int64_t N = 0, Nc = 0;
+  for (int k = 0; k < a.C; ++k) {
+    int64_t v = 0;
+    for (int r = 0; r < a.RS; ++r) v += a.nc2[(int64_t)r * a.C + k];
+    N += v;
+    if (k == c) Nc = v;
+  }
   if (t == 0) {
+    a.class_totals[c] = Nc;
     a.class_sums[c] = (a.kind == NB_MULTINOMIAL) ? Sc : Nc;
     if (Nc < a.min_files || Nc < 1) atomicOr(&a.status[kStatusFlags], kFlagMinFiles);
   }
@@ -349,6 +381,31 @@ int64_t train_slots(int32_t C, int32_t F, int64_t n) {
   return std::max<int64_t>(1, std::min(s, by_rows));
 }
 
+// Workspace: per-slot partials, per-slot class totals, and the RS
+// second-level partials of each.
+struct TrainWs {
+  int64_t S, RS;
+  size_t off_part, off_nc, off_part2, off_nc2, total;
+};
+
+TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
+  TrainWs w;
+  w.S = S;
+  w.RS = std::min<int64_t>(kReduceSplit, S);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, kAlign);
+    return at;
+  };
+  w.off_part = take((size_t)S * C * Fp * 8);
+  w.off_nc = take((size_t)S * C * 8);
+  w.off_part2 = take((size_t)w.RS * C * Fp * 8);
+  w.off_nc2 = take((size_t)w.RS * C * 8);
+  w.total = off;
+  return w;
+}
+
 int flags_to_status(int32_t flags) {
   if (flags & (kFlagBadLabel | kFlagNegative))
     return fail(NB_EDATA, (flags & kFlagBadLabel) ? "a label is outside [0, C)" : "a feature value is negative");
@@ -367,9 +424,7 @@ extern "C" {
 size_t nb_train_workspace_bytes(int32_t n_classes, int32_t n_features, int64_t n, int32_t xtype) {
   nb_layout L;
   if (!compute_layout(n_classes, n_features, &L) || n < 0 || elem_bytes(xtype) == 0) return 0;
-  const int64_t S = train_slots(n_classes, n_features, n);
-  return align_up((size_t)S * n_classes * L.padded_features * 8, kAlign) +
-         align_up((size_t)S * n_classes * 8, kAlign);
+  return train_ws(n_classes, L.padded_features, train_slots(n_classes, n_features, n)).total;
 }
 
 int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, const int32_t* y,
@@ -402,9 +457,12 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   int32_t* status = reinterpret_cast<int32_t*>(base + L.off_status);
   const int Fp = L.padded_features;
   const int64_t S = train_slots(C, F, n);
-  int64_t* part = static_cast<int64_t*>(workspace);
-  int64_t* nc_part = reinterpret_cast<int64_t*>(static_cast<uint8_t*>(workspace) +
-                                                align_up((size_t)S * C * Fp * 8, kAlign));
+  const TrainWs tw = train_ws(C, Fp, S);
+  uint8_t* wsb = static_cast<uint8_t*>(workspace);
+  int64_t* part = reinterpret_cast<int64_t*>(wsb + tw.off_part);
+  int64_t* nc_part = reinterpret_cast<int64_t*>(wsb + tw.off_nc);
+  int64_t* part2 = reinterpret_cast<int64_t*>(wsb + tw.off_part2);
+  int64_t* nc2 = reinterpret_cast<int64_t*>(wsb + tw.off_nc2);
 
   hipLaunchKernelGGL(init_status, dim3(1), dim3(64), 0, s, status);
   NB_HIP_CHECK(hipGetLastError());
@@ -433,14 +491,15 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   }
   NB_HIP_CHECK(hipGetLastError());
 
-  hipLaunchKernelGGL(reduce_counts, dim3((unsigned)((F + 255) / 256), (unsigned)C), dim3(256), 0, s, part,
-                     nc_part, (int)S, C, F, Fp, reinterpret_cast<int32_t*>(base + L.off_counts),
-                     reinterpret_cast<int64_t*>(base + L.off_class_totals), status);
+  hipLaunchKernelGGL(reduce_counts, dim3((unsigned)((F + 63) / 64), (unsigned)C, (unsigned)tw.RS), dim3(256), 0, s,
+                     part, nc_part, (int)S, C, F, Fp, part2, nc2);
   NB_HIP_CHECK(hipGetLastError());
 
   TableArgs ta;
-  ta.counts = reinterpret_cast<const int32_t*>(base + L.off_counts);
-  ta.class_totals = reinterpret_cast<const int64_t*>(base + L.off_class_totals);
+  ta.part2 = part2;
+  ta.nc2 = nc2;
+  ta.counts = reinterpret_cast<int32_t*>(base + L.off_counts);
+  ta.class_totals = reinterpret_cast<int64_t*>(base + L.off_class_totals);
   ta.class_sums = reinterpret_cast<int64_t*>(base + L.off_class_sums);
   ta.log_theta = reinterpret_cast<double*>(base + L.off_log_theta);
   ta.log_1m_theta = reinterpret_cast<double*>(base + L.off_log_1m_theta);
@@ -450,6 +509,8 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   ta.alpha = alpha;
   ta.F = F;
   ta.C = C;
+  ta.Fp = Fp;
+  ta.RS = (int32_t)tw.RS;
   ta.kind = m->kind;
   ta.min_files = min_files_per_class;
   hipLaunchKernelGGL(class_tables, dim3((unsigned)C), dim3(256), 0, s, ta);

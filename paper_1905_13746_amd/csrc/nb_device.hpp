@@ -37,9 +37,9 @@ __device__ __forceinline__ u32x4 load16_guarded(const uint8_t* p, int64_t avail)
 // Raw buffer resource over [base, base + bytes): loads at offsets beyond
 // `bytes` return zero instead of touching memory.  Word 3 is the gfx9-family
 // descriptor format for untyped dword access.
-// `bytes` must be >= 0; it is capped at 2^31 - 1 (the descriptor field).
+// `bytes` is clamped to [0, 2^31 - 1] (the descriptor field).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
-  const uint64_t b = (uint64_t)bytes;
+  const uint64_t b = (uint64_t)(bytes < 0 ? 0 : bytes);
   const int32_t n = (b >> 31) ? 0x7FFFFFFF : (int32_t)b;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
 }

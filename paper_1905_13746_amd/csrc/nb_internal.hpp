@@ -48,4 +48,10 @@ int elem_bytes(int32_t xtype);
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
+// Scoring launchers for more than two classes (arguments validated by nb_score).
+int launch_scoreC_valu(const nb_model* m, const nb_layout& L, const void* x, int32_t xtype, int64_t n, int64_t ld,
+                       int32_t wtype, int32_t* labels, float* log_post, float* scores, hipStream_t s);
+int launch_scoreC_mfma(const nb_model* m, const nb_layout& L, const void* x, int32_t xtype, int64_t n, int64_t ld,
+                       int32_t* labels, float* log_post, float* scores, hipStream_t s);
+
 }  // namespace nb

@@ -521,5 +521,10 @@ extern "C" int nb_score(const nb_model* m, const void* x, int32_t xtype, int64_t
     return fail(NB_EINVAL, "log_post and scores must be 8-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (m->n_classes == 2) return launch_score2(m, L, x, xtype, n, ld, wtype, labels, log_post, scores, s);
-  return fail(NB_EINVAL, "scoring for more than two classes is not built yet");
+  // BF16 tables with a full column tile of classes go to the matrix cores;
+  // everything else (the FP32 plain path, fewer classes, int32 features) to
+  // the vector ALUs
+  if (wtype == NB_W_BF16 && m->n_classes >= 16 && xtype != NB_X_I32)
+    return launch_scoreC_mfma(m, L, x, xtype, n, ld, labels, log_post, scores, s);
+  return launch_scoreC_valu(m, L, x, xtype, n, ld, wtype, labels, log_post, scores, s);
 }

@@ -1,0 +1,301 @@
+// Naive Bayes scoring with a BF16 table on the matrix cores (C >= 16):
+// s~[file, class] = sum_f g(x_f) W~[class, f] is a skinny GEMM
+// (M = files, N = classes, K = features) once the class count fills an MFMA
+// column tile.  Feature bytes (uint8 counts or FP8-e4m3) convert exactly to
+// BF16; products accumulate in FP32 (v_mfma_f32_16x16x32_bf16).
+//
+// Mapping.  A wave owns MT tiles of 16 files and all NT tiles of 16 classes.
+// The K order inside a tile is free (the same permutation on A and B leaves
+// the sum unchanged), so each lane streams 16 contiguous feature bytes of
+// its file per 64-feature window (lane group q = lane / 16 takes bytes
+// 16q .. 16q + 15) and feeds two MFMAs with them; the matching B fragment is
+// 8 contiguous BF16 entries of one class row, read from a table slice staged
+// in LDS (class-major, padded rows: conflict-free 16-byte reads).  The 4
+// waves of a workgroup share each staged slice.  After the K loop the 16x16
+// accumulator tiles (lane l holds rows 4*(l/16)..+3 of column l%16) are
+// reduced across the 16 lanes of each column group for the max / log-sum-exp
+// epilogue; labels take the lowest class index among maxima.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "nb_device.hpp"
+#include "nb_internal.hpp"
+
+namespace nb {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kWindow = 64;                 // features per window (one 16-byte load per lane)
+constexpr int kSliceElems = 32768;          // BF16 table entries staged per slice (64 KiB)
+
+struct ScoreMArgs {
+  const uint8_t* x;
+  int64_t ld_bytes;
+  int64_t n;
+  int64_t total_bytes;
+  const uint16_t* rows16;   // [P+1][Fp] class-major BF16 rows (centred rows, aux row C)
+  const float* row_bias;    // [P+1]
+  int32_t* labels;
+  float* log_post;
+  float* scores;
+  int32_t F, Fp, C, ns;     // ns: rows used (C, or C + 1 with the aux row)
+};
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  // exact for the small integers and FP8 values converted here: keep the
+  // upper halves of the two FP32 images
+  return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
+}
+
+// 16 feature bytes -> 16 BF16 values (two MFMA A operands).
+template <int XT, bool BIN>
+__device__ __forceinline__ void to_bf16(const dev::u32x4& v, dev::u32x4& a0, dev::u32x4& a1) {
+  uint32_t o[8];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const uint32_t u = v[d];
+    float f0, f1, f2, f3;
+    if (XT == NB_X_U8) {
+      f0 = (float)(u & 0xFFu);
+      f1 = (float)((u >> 8) & 0xFFu);
+      f2 = (float)((u >> 16) & 0xFFu);
+      f3 = (float)(u >> 24);
+    } else {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(u, false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(u, true);
+      f0 = lo[0];
+      f1 = lo[1];
+      f2 = hi[0];
+      f3 = hi[1];
+    }
+    if (BIN) {
+      f0 = f0 > 0.0f ? 1.0f : 0.0f;
+      f1 = f1 > 0.0f ? 1.0f : 0.0f;
+      f2 = f2 > 0.0f ? 1.0f : 0.0f;
+      f3 = f3 > 0.0f ? 1.0f : 0.0f;
+    }
+    o[2 * d] = pack_bf16(f0, f1);
+    o[2 * d + 1] = pack_bf16(f2, f3);
+  }
+  a0 = dev::u32x4{o[0], o[1], o[2], o[3]};
+  a1 = dev::u32x4{o[4], o[5], o[6], o[7]};
+}
+
+__device__ __forceinline__ f32x4 mfma(const dev::u32x4& a, const dev::u32x4& b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+template <int XT, int NT, int MT, bool BIN>
+__global__ __launch_bounds__(kThreads) void scoreM_kernel(ScoreMArgs a) {
+  constexpr int NCOL = 16 * NT;
+  constexpr int KT = kSliceElems / NCOL;            // features per staged slice
+  constexpr int RS = KT + 8;                        // padded row stride (BF16 entries)
+  constexpr int FILES = 16 * MT;                    // files per wave
+  __shared__ __attribute__((aligned(16))) uint16_t tbl[NCOL * RS];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col = lane & 15, q = lane >> 4;
+  const int64_t ld = a.ld_bytes;
+  const int64_t per_tile = (int64_t)FILES * kWaves;
+  const int64_t ntile = (a.n + per_tile - 1) / per_tile;
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t row0 = tile * per_tile + (int64_t)wave * FILES;   // first file of this wave
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bool wave_full = row0 + FILES <= a.n;
+
+    for (int k0 = 0; k0 < a.F; k0 += KT) {
+      const int kn = min(KT, a.Fp - k0);
+      __syncthreads();
+      // stage rows [0, NCOL) x features [k0, k0 + kn) (16-byte pieces; rows >= ns are zero)
+      const int pieces_per_row = kn / 8;
+      for (int i = threadIdx.x; i < NCOL * pieces_per_row; i += kThreads) {
+        const int r = i / pieces_per_row, p = i - r * pieces_per_row;
+        dev::u32x4 v = {0u, 0u, 0u, 0u};
+        if (r < a.ns) v = *reinterpret_cast<const dev::u32x4*>(a.rows16 + (int64_t)r * a.Fp + k0 + 8 * p);
+        *reinterpret_cast<dev::u32x4*>(tbl + r * RS + 8 * p) = v;
+      }
+      __syncthreads();
+      const int kend = min(kn, a.F - k0);
+      for (int w0 = 0; w0 < kend; w0 += kWindow) {
+        // A: file (row0 + 16 mt + col), bytes [k0 + w0 + 16 q, +16)
+        const int64_t wbase = row0 * ld + (int64_t)(k0 + w0);
+        const auto rsrc = dev::make_rsrc(a.x + wbase, a.total_bytes - wbase);
+        const bool safe = wave_full && (row0 + FILES - 1) * ld + k0 + w0 + kWindow <= a.total_bytes;
+        dev::u32x4 xv[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int r = 16 * mt + col;
+          const uint32_t rel = (uint32_t)(r * ld) + 16 * q;
+          if (safe) {
+            xv[mt] = dev::buffer_load16(rsrc, rel);
+          } else {
+            xv[mt] = dev::u32x4{0u, 0u, 0u, 0u};
+            if (row0 + r < a.n) xv[mt] = dev::load16_guarded(a.x + wbase + rel, a.total_bytes - (wbase + rel));
+          }
+          if (XT == NB_X_FP8 && k0 + w0 + 16 * q + 16 > a.F) {   // NaN encodings past the last feature
+            const int nv = max(0, a.F - (k0 + w0 + 16 * q));
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              const int nb = min(4, max(0, nv - 4 * d));
+              xv[mt][d] &= (nb >= 4) ? ~0u : ((1u << (8 * nb)) - 1u);
+            }
+          }
+        }
+        dev::u32x4 av[MT][2];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) to_bf16<XT, BIN>(xv[mt], av[mt][0], av[mt][1]);
+        // B: class (16 nt + col), features [w0 + 16 q + 8 t, +8)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const uint16_t* tb = tbl + (16 * nt + col) * RS + w0 + 16 * q;
+          const dev::u32x4 b0 = *reinterpret_cast<const dev::u32x4*>(tb);
+          const dev::u32x4 b1 = *reinterpret_cast<const dev::u32x4*>(tb + 8);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            acc[mt][nt] = mfma(av[mt][0], b0, acc[mt][nt]);
+            acc[mt][nt] = mfma(av[mt][1], b1, acc[mt][nt]);
+          }
+        }
+      }
+    }
+
+    // epilogue: lane holds files 4q + i (i < 4) of each M tile, class 16 nt + col
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + 16 * mt + 4 * q + i;
+        float s[NT];
+        float m = -INFINITY;
+        int best = 1 << 30;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int c = 16 * nt + col;
+          s[nt] = acc[mt][nt][i] + ((c < a.ns) ? a.row_bias[c] : 0.0f);
+          if (c < a.C && s[nt] > m) {
+            m = s[nt];
+            best = c;
+          }
+        }
+        // max and lowest arg-max over the 16 lanes of this column group
+#pragma unroll
+        for (int sh = 1; sh < 16; sh <<= 1) {
+          const float om = __shfl_xor(m, sh);
+          const int ob = __shfl_xor(best, sh);
+          if (om > m || (om == m && ob < best)) {
+            m = om;
+            best = ob;
+          }
+        }
+        float z = 0.0f;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          if (16 * nt + col < a.C) z += __expf(s[nt] - m);
+#pragma unroll
+        for (int sh = 1; sh < 16; sh <<= 1) z += __shfl_xor(z, sh);
+        const float lse = m + __logf(z);
+        // aux row (raw-score offset) lives in column C
+        float aux = 0.0f;
+        if (a.ns > a.C) {
+          float mine = 0.0f;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            if (16 * nt + col == a.C) mine = s[nt];
+          aux = __shfl(mine, (lane & ~15) | (a.C & 15));
+        }
+        if (row < a.n) {
+          if (a.labels && col == 0) a.labels[row] = best;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const int c = 16 * nt + col;
+            if (c < a.C) {
+              if (a.log_post) a.log_post[row * a.C + c] = s[nt] - lse;
+              if (a.scores) a.scores[row * a.C + c] = s[nt] + aux;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+using KernelFn = void (*)(ScoreMArgs);
+
+template <int XT, int NT>
+KernelFn pick_bin(bool bin) {
+  constexpr int MT = (NT >= 8) ? 1 : 2;
+  return bin ? scoreM_kernel<XT, NT, MT, true> : scoreM_kernel<XT, NT, MT, false>;
+}
+
+template <int XT>
+KernelFn pick_nt(int nt, bool bin) {
+  if (nt <= 1) return pick_bin<XT, 1>(bin);
+  if (nt <= 2) return pick_bin<XT, 2>(bin);
+  if (nt <= 4) return pick_bin<XT, 4>(bin);
+  if (nt <= 8) return pick_bin<XT, 8>(bin);
+  if (nt <= 16) return pick_bin<XT, 16>(bin);
+  return nullptr;
+}
+
+int resident_per_cu(const void* fn) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, 0) != hipSuccess || per < 1) per = 1;
+  cache[fn] = per;
+  return per;
+}
+
+}  // namespace
+
+int launch_scoreC_mfma(const nb_model* m, const nb_layout& L, const void* x, int32_t xtype, int64_t n, int64_t ld,
+                       int32_t* labels, float* log_post, float* scores, hipStream_t s) {
+  const int C = m->n_classes;
+  const int ns = C + (scores ? 1 : 0);
+  const int nt = (ns + 15) / 16;
+  const bool bin = m->kind == NB_BERNOULLI;
+  KernelFn fn = (xtype == NB_X_U8) ? pick_nt<NB_X_U8>(nt, bin) : pick_nt<NB_X_FP8>(nt, bin);
+  if (!fn) return fail(NB_EINVAL, "matrix-core scoring supports up to 256 score columns (255 classes with raw scores)");
+  const int mt = (nt > 4) ? 1 : 2;
+  const uint8_t* base = static_cast<const uint8_t*>(m->dev);
+  ScoreMArgs a;
+  a.x = static_cast<const uint8_t*>(x);
+  a.ld_bytes = ld;
+  a.n = n;
+  a.total_bytes = (n - 1) * ld + m->n_features;
+  a.rows16 = reinterpret_cast<const uint16_t*>(base + L.off_form_bf16);
+  a.row_bias = reinterpret_cast<const float*>(base + L.off_form_bias);
+  a.labels = labels;
+  a.log_post = log_post;
+  a.scores = scores;
+  a.F = m->n_features;
+  a.Fp = L.padded_features;
+  a.C = C;
+  a.ns = ns;
+  const int64_t per_tile = (int64_t)16 * mt * kWaves;
+  if (per_tile * a.ld_bytes >= ((int64_t)1 << 31))
+    return fail(NB_EINVAL, "row stride too large (a tile of rows must span < 2 GiB)");
+  const int64_t ntile = (n + per_tile - 1) / per_tile;
+  const int64_t cap = (int64_t)resident_per_cu(reinterpret_cast<const void*>(fn)) * device_cu_count();
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(ntile, cap));
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), 0, s, a);
+  NB_HIP_CHECK(hipGetLastError());
+  return NB_OK;
+}
+
+}  // namespace nb

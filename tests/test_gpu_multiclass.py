@@ -1,0 +1,137 @@
+"""GPU parity for more than two classes (malware-family style models):
+vector-ALU FP32 and BF16 paths, matrix-core BF16 path (uint8 and FP8
+features), against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1905_13746_amd as nbg
+from oracle import nb, precision as P
+from synth import workloads as W
+from tests.parity import X_FP8, X_I32, X_U8, assert_scores, assert_tables, to_np
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def family(C, F, wid=6, p_zero=0.8, clip=True):
+    """Dirichlet(1) class priors for up to 17 classes; balanced beyond, so every
+    class keeps enough training files."""
+    prior = np.random.default_rng(C * 1000 + F).dirichlet(np.ones(C)) if C <= 17 else None
+    return W.Workload(wid=wid, n_classes=C, n_features=F, p_zero=p_zero, clip255=clip, group=C * 8192 + F,
+                      prior=prior)
+
+
+def _train(wl, n, kind):
+    X, y = wl.train_set(n, device=DEV)
+    m = nbg.Model(wl.n_classes, wl.n_features, kind)
+    nbg.train(m, X, y)
+    om = nb.train(to_np(X), to_np(y), wl.n_classes, kind)
+    return m, om
+
+
+VALU = [(3, 1000), (5, 100), (7, 513), (16, 4096), (31, 300)]
+
+
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+@pytest.mark.parametrize("C,F", VALU, ids=[f"C{c}_F{f}" for c, f in VALU])
+def test_fp32_vector_path(C, F, kind):
+    _case(f"fp32 valu C={C} F={F} {kind}")
+    wl = family(C, F)
+    m, om = _train(wl, 6000, kind)
+    assert m.trained
+    assert_tables(m, om, kind)
+    Xt, _ = wl.test_set(1537, device=DEV)
+    with_scores = C + 1 <= 32
+    lab, lp, sc = nbg.score(m, Xt, scores=with_scores)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(Xt), to_np(lab), to_np(lp), to_np(sc) if with_scores else None)
+
+
+def test_int32_features_three_classes():
+    wl = family(3, 64, p_zero=0.7, clip=False)
+    m, om = _train(wl, 3000, nb.MULTINOMIAL)
+    Xt, _ = wl.test_set(999, device=DEV)
+    lab, lp, sc = nbg.score(m, Xt, scores=True)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(Xt), to_np(lab), to_np(lp), to_np(sc), xtype=X_I32)
+
+
+@pytest.mark.parametrize("C,F", [(5, 1000), (12, 300)])
+def test_bf16_vector_path(C, F):
+    _case(f"bf16 valu C={C} F={F}")
+    wl = family(C, F)
+    m, om = _train(wl, 6000, nb.MULTINOMIAL)
+    Xt, _ = wl.test_set(2000, device=DEV)
+    lab, lp, sc = nbg.score(m, Xt, wtype=nbg.W_BF16, scores=True)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(Xt), to_np(lab), to_np(lp), to_np(sc), wtype=nbg.W_BF16)
+
+
+MFMA = [(16, 4096, 2000), (16, 1000, 1), (16, 1000, 63), (16, 1000, 129), (17, 640, 777), (40, 500, 1500),
+        (130, 256, 300)]
+
+
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+@pytest.mark.parametrize("C,F,n", MFMA, ids=[f"C{c}_F{f}_n{n}" for c, f, n in MFMA])
+def test_bf16_matrix_core_path(C, F, n, kind):
+    _case(f"bf16 mfma C={C} F={F} n={n} {kind}")
+    wl = family(C, F)
+    m, om = _train(wl, 5000, kind)
+    Xt, _ = wl.test_set(n, device=DEV)
+    lab, lp, sc = nbg.score(m, Xt, wtype=nbg.W_BF16, scores=True)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(Xt), to_np(lab), to_np(lp), to_np(sc), wtype=nbg.W_BF16)
+    lab2, lp2, _ = nbg.score(m, Xt, wtype=nbg.W_BF16)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(Xt), to_np(lab2), to_np(lp2), None, wtype=nbg.W_BF16)
+
+
+@pytest.mark.parametrize("C,F", [(16, 4096), (20, 1000)])
+def test_bf16_matrix_core_fp8_features(C, F):
+    _case(f"bf16 mfma fp8 C={C} F={F}")
+    wl = family(C, F)
+    m, om = _train(wl, 5000, nb.MULTINOMIAL)
+    Xt, _ = wl.test_set(1500, device=DEV)
+    q8 = W.to_fp8_e4m3(Xt)
+    lab, lp, sc = nbg.score(m, q8, wtype=nbg.W_BF16, fp8=True, scores=True)
+    torch.cuda.synchronize()
+    assert_scores(om, P.e4m3_value(to_np(q8)), to_np(lab), to_np(lp), to_np(sc), wtype=nbg.W_BF16,
+                  xtype=X_FP8)
+
+
+@pytest.mark.parametrize("wtype", [0, 1])
+def test_multiclass_strided_rows(wtype):
+    C, F, ld, n = 16, 1000, 1040, 301
+    wl = family(C, F)
+    m, om = _train(wl, 5000, nb.MULTINOMIAL)
+    X, _ = wl.test_set(n, device=DEV)
+    big = torch.zeros((n, ld), dtype=torch.uint8, device=DEV)
+    big[:, :F] = X
+    lab, lp, sc = nbg.score(m, big[:, :F], wtype=wtype, scores=True)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(X), to_np(lab), to_np(lp), to_np(sc), wtype=wtype)
+
+
+@pytest.mark.parametrize("wtype", [0, 1])
+def test_multiclass_batch_invariance(wtype):
+    wl = family(16, 1000)
+    m, _ = _train(wl, 5000, nb.MULTINOMIAL)
+    X, _ = wl.test_set(3000, device=DEV)
+    full = nbg.score(m, X, wtype=wtype, scores=True)
+    for a, b in ((0, 1), (100, 229), (2900, 3000)):
+        part = nbg.score(m, X[a:b], wtype=wtype, scores=True)
+        for u, v in zip(full, part):
+            assert torch.equal(u[a:b], v)
+
+
+def test_more_classes_than_vector_path_rejected():
+    m = nbg.Model(40, 100, "multinomial")
+    X = torch.zeros((10, 100), dtype=torch.uint8, device=DEV)
+    with pytest.raises(nbg.NBError):
+        nbg.score(m, X)                      # FP32 table, 40 classes
+    nbg.score(m, X, wtype=nbg.W_BF16)        # matrix cores take it

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "nb_device.hpp"
 #include "nb_internal.hpp"
@@ -89,6 +90,70 @@ __device__ __forceinline__ void to_bf16(const dev::u32x4& v, dev::u32x4& a0, dev
 __device__ __forceinline__ f32x4 mfma(const dev::u32x4& a, const dev::u32x4& b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
                                                  0, 0, 0);
+}
+
+// Epilogue of a 16*MT-file tile: lane holds files 4q + i (i < 4) of each M
+// tile for class 16 nt + col.  Max and lowest arg-max over the 16 lanes of a
+// column group, log-sum-exp, then labels, log posteriors and raw scores.
+template <int NT, int MT>
+__device__ __forceinline__ void epilogue(const ScoreMArgs& a, f32x4 (&acc)[MT][NT], int lane, int64_t row0) {
+  const int col = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = row0 + 16 * mt + 4 * q + i;
+      float s[NT];
+      float m = -INFINITY;
+      int best = 1 << 30;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int c = 16 * nt + col;
+        s[nt] = acc[mt][nt][i] + ((c < a.ns) ? a.row_bias[c] : 0.0f);
+        if (c < a.C && s[nt] > m) {
+          m = s[nt];
+          best = c;
+        }
+      }
+      // max and lowest arg-max over the 16 lanes of this column group
+#pragma unroll
+      for (int sh = 1; sh < 16; sh <<= 1) {
+        const float om = __shfl_xor(m, sh);
+        const int ob = __shfl_xor(best, sh);
+        if (om > m || (om == m && ob < best)) {
+          m = om;
+          best = ob;
+        }
+      }
+      float z = 0.0f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        if (16 * nt + col < a.C) z += __expf(s[nt] - m);
+#pragma unroll
+      for (int sh = 1; sh < 16; sh <<= 1) z += __shfl_xor(z, sh);
+      const float lse = m + __logf(z);
+      // aux row (raw-score offset) lives in column C
+      float aux = 0.0f;
+      if (a.ns > a.C) {
+        float mine = 0.0f;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          if (16 * nt + col == a.C) mine = s[nt];
+        aux = __shfl(mine, (lane & ~15) | (a.C & 15));
+      }
+      if (row < a.n) {
+        if (a.labels && col == 0) a.labels[row] = best;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int c = 16 * nt + col;
+          if (c < a.C) {
+            if (a.log_post) a.log_post[row * a.C + c] = s[nt] - lse;
+            if (a.scores) a.scores[row * a.C + c] = s[nt] + aux;
+          }
+        }
+      }
+    }
+  }
 }
 
 template <int XT, int NT, int MT, bool BIN>
@@ -171,94 +236,188 @@ __global__ __launch_bounds__(kThreads) void scoreM_kernel(ScoreMArgs a) {
       }
     }
 
-    // epilogue: lane holds files 4q + i (i < 4) of each M tile, class 16 nt + col
+    epilogue<NT, MT>(a, acc, lane, row0);
+  }
+}
+
+// Whole-table variant: the BF16 rows of all NT column tiles fit in LDS, so a
+// persistent workgroup of kWavesFull waves stages the table once and then
+// streams files with no barriers: each wave walks its 16*MT-file tiles in
+// groups of KU 64-feature windows, double-buffered (the loads of group g + 1
+// are in flight while group g is converted and multiplied).
+#ifndef NB_MFMA_WAVES
+#define NB_MFMA_WAVES 8
+#endif
+#ifndef NB_MFMA_KU
+#define NB_MFMA_KU 4
+#endif
+#ifndef NB_MFMA_MT
+#define NB_MFMA_MT 2
+#endif
+constexpr int kWavesFull = NB_MFMA_WAVES;
+constexpr int kThreadsFull = 64 * kWavesFull;
+constexpr int kKU = NB_MFMA_KU;             // windows per group
+constexpr int kMTFull = NB_MFMA_MT;         // 16-file tiles per wave (few column tiles)
+
+template <int XT, int NT, int MT, bool BIN>
+__global__ __launch_bounds__(kThreadsFull) void scoreM_full_kernel(ScoreMArgs a) {
+  constexpr int NCOL = 16 * NT;
+  constexpr int FILES = 16 * MT;
+  constexpr int GB = kKU * kWindow;                 // features per group
+  extern __shared__ __attribute__((aligned(16))) uint16_t tblf[];   // [NCOL][RS]
+  const int RS = a.Fp + 8;
+
+  // stage the whole table (rows >= ns are zero)
+  const int pieces_per_row = a.Fp / 8;
+  for (int i = threadIdx.x; i < NCOL * pieces_per_row; i += kThreadsFull) {
+    const int r = i / pieces_per_row, p = i - r * pieces_per_row;
+    dev::u32x4 v = {0u, 0u, 0u, 0u};
+    if (r < a.ns) v = *reinterpret_cast<const dev::u32x4*>(a.rows16 + (int64_t)r * a.Fp + 8 * p);
+    *reinterpret_cast<dev::u32x4*>(tblf + r * RS + 8 * p) = v;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col = lane & 15, q = lane >> 4;
+  const int64_t ld = a.ld_bytes;
+  const int64_t nwtile = (a.n + FILES - 1) / FILES;                 // wave tiles
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesFull;
+  const int ngroups = (a.F + GB - 1) / GB;
+  uint32_t rel[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
+  for (int mt = 0; mt < MT; ++mt) rel[mt] = (uint32_t)((16 * mt + col) * ld) + 16 * q;
+
+  // one wave tile of FILES files; FAST: all rows present and every load in bounds
+  auto tile = [&](int64_t row0, auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    f32x4 acc[MT][NT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t row = row0 + 16 * mt + 4 * q + i;
-        float s[NT];
-        float m = -INFINITY;
-        int best = 1 << 30;
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    auto load_group = [&](int g, dev::u32x4 (&dst)[kKU][MT]) {
+      const int64_t wbase = row0 * ld + (int64_t)g * GB;
+      if (FAST) {
+        const auto rsrc = dev::make_rsrc(a.x + wbase, a.total_bytes - wbase);
+#pragma unroll
+        for (int u = 0; u < kKU; ++u)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) dst[u][mt] = dev::buffer_load16(rsrc, rel[mt] + u * kWindow);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kKU; ++u)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            dst[u][mt] = dev::u32x4{0u, 0u, 0u, 0u};
+            const int64_t off = wbase + rel[mt] + u * kWindow;
+            if (row0 + 16 * mt + col < a.n) dst[u][mt] = dev::load16_guarded(a.x + off, a.total_bytes - off);
+          }
+      }
+    };
+    auto compute_group = [&](int g, dev::u32x4 (&src)[kKU][MT]) {
+#pragma unroll
+      for (int u = 0; u < kKU; ++u) {
+        const int f0 = g * GB + u * kWindow;         // first feature of the window
+        dev::u32x4 av[MT][2];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          dev::u32x4 xv = src[u][mt];
+          if (XT == NB_X_FP8 && f0 + 16 * q + 16 > a.F) {   // NaN encodings past the last feature
+            const int nv = max(0, a.F - (f0 + 16 * q));
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              const int nb = min(4, max(0, nv - 4 * d));
+              xv[d] &= (nb >= 4) ? ~0u : ((1u << (8 * nb)) - 1u);
+            }
+          }
+          to_bf16<XT, BIN>(xv, av[mt][0], av[mt][1]);
+        }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const int c = 16 * nt + col;
-          s[nt] = acc[mt][nt][i] + ((c < a.ns) ? a.row_bias[c] : 0.0f);
-          if (c < a.C && s[nt] > m) {
-            m = s[nt];
-            best = c;
-          }
-        }
-        // max and lowest arg-max over the 16 lanes of this column group
+          const uint16_t* tb = tblf + (16 * nt + col) * RS + f0 + 16 * q;
+          const dev::u32x4 b0 = *reinterpret_cast<const dev::u32x4*>(tb);
+          const dev::u32x4 b1 = *reinterpret_cast<const dev::u32x4*>(tb + 8);
 #pragma unroll
-        for (int sh = 1; sh < 16; sh <<= 1) {
-          const float om = __shfl_xor(m, sh);
-          const int ob = __shfl_xor(best, sh);
-          if (om > m || (om == m && ob < best)) {
-            m = om;
-            best = ob;
-          }
-        }
-        float z = 0.0f;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          if (16 * nt + col < a.C) z += __expf(s[nt] - m);
-#pragma unroll
-        for (int sh = 1; sh < 16; sh <<= 1) z += __shfl_xor(z, sh);
-        const float lse = m + __logf(z);
-        // aux row (raw-score offset) lives in column C
-        float aux = 0.0f;
-        if (a.ns > a.C) {
-          float mine = 0.0f;
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-            if (16 * nt + col == a.C) mine = s[nt];
-          aux = __shfl(mine, (lane & ~15) | (a.C & 15));
-        }
-        if (row < a.n) {
-          if (a.labels && col == 0) a.labels[row] = best;
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
-            const int c = 16 * nt + col;
-            if (c < a.C) {
-              if (a.log_post) a.log_post[row * a.C + c] = s[nt] - lse;
-              if (a.scores) a.scores[row * a.C + c] = s[nt] + aux;
-            }
+          for (int mt = 0; mt < MT; ++mt) {
+            acc[mt][nt] = mfma(av[mt][0], b0, acc[mt][nt]);
+            acc[mt][nt] = mfma(av[mt][1], b1, acc[mt][nt]);
           }
         }
       }
+    };
+    dev::u32x4 bufA[kKU][MT], bufB[kKU][MT];
+    load_group(0, bufA);
+    for (int g = 0; g < ngroups; g += 2) {
+      // the prefetch past the last group re-reads the last one (an L2 hit),
+      // so every iteration issues the same loads
+      load_group(min(g + 1, ngroups - 1), bufB);
+      compute_group(g, bufA);
+      if (g + 1 >= ngroups) break;
+      load_group(min(g + 2, ngroups - 1), bufA);
+      compute_group(g + 1, bufB);
     }
+    epilogue<NT, MT>(a, acc, lane, row0);
+  };
+
+  for (int64_t wt = (int64_t)blockIdx.x * kWavesFull + wave; wt < nwtile; wt += nwaves) {
+    const int64_t row0 = wt * FILES;
+    const bool full = row0 + FILES <= a.n && (row0 + FILES - 1) * ld + (int64_t)ngroups * GB <= a.total_bytes;
+    if (full) tile(row0, std::true_type{});
+    else tile(row0, std::false_type{});
   }
 }
 
 using KernelFn = void (*)(ScoreMArgs);
 
+// column tiles rounded up to a compiled width (extra columns are zero rows)
+int round_nt(int nt) { return nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : nt <= 8 ? 8 : nt <= 16 ? 16 : 0; }
+
 template <int XT, int NT>
-KernelFn pick_bin(bool bin) {
+KernelFn pick_bin(bool bin, bool full) {
   constexpr int MT = (NT >= 8) ? 1 : 2;
+  constexpr int MTF = (NT >= 8) ? 1 : (NT >= 4 ? 2 : kMTFull);
+  if (full) return bin ? scoreM_full_kernel<XT, NT, MTF, true> : scoreM_full_kernel<XT, NT, MTF, false>;
   return bin ? scoreM_kernel<XT, NT, MT, true> : scoreM_kernel<XT, NT, MT, false>;
 }
 
 template <int XT>
-KernelFn pick_nt(int nt, bool bin) {
-  if (nt <= 1) return pick_bin<XT, 1>(bin);
-  if (nt <= 2) return pick_bin<XT, 2>(bin);
-  if (nt <= 4) return pick_bin<XT, 4>(bin);
-  if (nt <= 8) return pick_bin<XT, 8>(bin);
-  if (nt <= 16) return pick_bin<XT, 16>(bin);
-  return nullptr;
+KernelFn pick_nt(int ntr, bool bin, bool full) {
+  switch (ntr) {
+    case 1: return pick_bin<XT, 1>(bin, full);
+    case 2: return pick_bin<XT, 2>(bin, full);
+    case 4: return pick_bin<XT, 4>(bin, full);
+    case 8: return pick_bin<XT, 8>(bin, full);
+    case 16: return pick_bin<XT, 16>(bin, full);
+    default: return nullptr;
+  }
 }
 
-int resident_per_cu(const void* fn) {
+int resident_per_cu(const void* fn, int threads, size_t lds) {
   static std::mutex mu;
-  static std::map<const void*, int> cache;
+  static std::map<std::pair<const void*, size_t>, int> cache;
   std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(fn);
+  auto key = std::make_pair(fn, lds);
+  auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, 0) != hipSuccess || per < 1) per = 1;
-  cache[fn] = per;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, lds) != hipSuccess || per < 1) per = 1;
+  cache[key] = per;
   return per;
+}
+
+int max_lds_per_block() {
+  static int v = 0;
+  if (v == 0) {
+    int dev = 0, b = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0)
+      v = b;
+    else
+      v = 64 * 1024;
+  }
+  return v;
 }
 
 }  // namespace
@@ -267,11 +426,13 @@ int launch_scoreC_mfma(const nb_model* m, const nb_layout& L, const void* x, int
                        int32_t* labels, float* log_post, float* scores, hipStream_t s) {
   const int C = m->n_classes;
   const int ns = C + (scores ? 1 : 0);
-  const int nt = (ns + 15) / 16;
+  const int ntr = round_nt((ns + 15) / 16);
+  if (ntr == 0) return fail(NB_EINVAL, "matrix-core scoring supports up to 256 score columns (255 classes with raw scores)");
   const bool bin = m->kind == NB_BERNOULLI;
-  KernelFn fn = (xtype == NB_X_U8) ? pick_nt<NB_X_U8>(nt, bin) : pick_nt<NB_X_FP8>(nt, bin);
-  if (!fn) return fail(NB_EINVAL, "matrix-core scoring supports up to 256 score columns (255 classes with raw scores)");
-  const int mt = (nt > 4) ? 1 : 2;
+  const size_t lds_full = (size_t)16 * ntr * (L.padded_features + 8) * sizeof(uint16_t);
+  const bool full = lds_full <= (size_t)max_lds_per_block();
+  const int mt = (ntr >= 8) ? 1 : (!full ? 2 : (ntr >= 4 ? 2 : kMTFull));
+  KernelFn fn = (xtype == NB_X_U8) ? pick_nt<NB_X_U8>(ntr, bin, full) : pick_nt<NB_X_FP8>(ntr, bin, full);
   const uint8_t* base = static_cast<const uint8_t*>(m->dev);
   ScoreMArgs a;
   a.x = static_cast<const uint8_t*>(x);
@@ -287,13 +448,25 @@ int launch_scoreC_mfma(const nb_model* m, const nb_layout& L, const void* x, int
   a.Fp = L.padded_features;
   a.C = C;
   a.ns = ns;
-  const int64_t per_tile = (int64_t)16 * mt * kWaves;
-  if (per_tile * a.ld_bytes >= ((int64_t)1 << 31))
+  const int64_t files = (int64_t)16 * mt;
+  if (files * kWavesFull * a.ld_bytes >= ((int64_t)1 << 31))
     return fail(NB_EINVAL, "row stride too large (a tile of rows must span < 2 GiB)");
-  const int64_t ntile = (n + per_tile - 1) / per_tile;
-  const int64_t cap = (int64_t)resident_per_cu(reinterpret_cast<const void*>(fn)) * device_cu_count();
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(ntile, cap));
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), 0, s, a);
+  if (full) {
+    NB_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_full));
+    const int64_t nwtile = (n + files - 1) / files;
+    const int64_t want = (nwtile + kWavesFull - 1) / kWavesFull;
+    const int64_t cap =
+        (int64_t)resident_per_cu(reinterpret_cast<const void*>(fn), kThreadsFull, lds_full) * device_cu_count();
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreadsFull), lds_full, s, a);
+  } else {
+    const int64_t per_tile = files * kWaves;
+    const int64_t ntile = (n + per_tile - 1) / per_tile;
+    const int64_t cap = (int64_t)resident_per_cu(reinterpret_cast<const void*>(fn), kThreads, 0) * device_cu_count();
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(ntile, cap));
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), 0, s, a);
+  }
   NB_HIP_CHECK(hipGetLastError());
   return NB_OK;
 }

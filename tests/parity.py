@@ -15,7 +15,9 @@ Tolerances, derived from the arithmetic of each GPU path:
     sums take twice that to allow truncating accumulation).  Raw scores add
     the bounds of the rows they combine plus the final additions; log
     posteriors add the row bounds and 1e-5 for the hardware exp/log;
-  * posteriors: 1e-4 absolute (stated by the method's targets);
+  * posteriors: 1e-4 absolute on the FP32 path (stated by the method's
+    targets); with a BF16 table the error is stated and bounded through the
+    log-posterior bound, p |e^tol - 1|;
   * labels: identical wherever the oracle's top-1 minus top-2 margin exceeds
     max(1e-3, the certified band): twice the largest centred-row bound, or
     the log-odds bound for two classes.
@@ -137,7 +139,10 @@ def assert_scores(om, X, labels, log_post, scores, wtype=W_F32, xtype=X_U8):
         tol = lp_tol[:, None] if C == 2 else lp_tol
         assert (err <= tol).all(), f"log-posterior error {err.max()} above bound (worst ratio {(err / tol).max():.3g})"
         perr = np.abs(np.exp(log_post.astype(np.float64)) - np.exp(d.log_post))
-        assert perr.max() <= 1e-4, f"posterior error {perr.max()}"
+        if wtype == W_F32:
+            assert perr.max() <= 1e-4, f"posterior error {perr.max()}"
+        else:   # reduced precision: the error is stated, bounded through the log posteriors
+            assert (perr <= np.exp(d.log_post) * np.expm1(tol)).all(), f"posterior error {perr.max()}"
         stats["log_post_max_err"] = float(err.max())
         stats["post_max_err"] = float(perr.max())
     if labels is not None:

@@ -34,7 +34,7 @@ def _train(wl, n, kind):
     return m, om
 
 
-VALU = [(3, 1000), (5, 100), (7, 513), (16, 4096), (31, 300)]
+VALU = [(3, 1000), (5, 100), (7, 516), (16, 4096), (31, 300)]
 
 
 @pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])

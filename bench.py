@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--fill-inputs", action="store_true",
+                    help="constant-filled inputs instead of the seeded generator (for hardware-counter runs: "
+                         "the kernels' memory traffic does not depend on feature values)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "score2_u8_F1000_traffic.json"))
     return ap.parse_args()
 
@@ -207,8 +210,15 @@ def main():
 
     F = args.features
     wl = W.binary_u8(F)
-    Xtr, ytr = wl.train_set(args.n_train, device="cuda")
-    Xte, _ = wl.test_set(args.n_test, device="cuda")
+    if args.fill_inputs:
+        Xtr = torch.full((args.n_train, F), 1, dtype=torch.uint8, device="cuda")
+        ytr = torch.zeros(args.n_train, dtype=torch.int32, device="cuda")
+        ytr[1::2] = 1
+        Xte = torch.full((args.n_test, F), 2, dtype=torch.uint8, device="cuda")
+        args.no_cpu = args.no_extras = True
+    else:
+        Xtr, ytr = wl.train_set(args.n_train, device="cuda")
+        Xte, _ = wl.test_set(args.n_test, device="cuda")
     model = nbg.Model(2, F, "multinomial")
     ws = nbg.train_workspace(model, args.n_train)
     n = args.n_test

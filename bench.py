@@ -19,13 +19,21 @@ step's inputs.  Extra objects (skip with --no-extras):
   precision  16 classes, F = 4096, 4,000,000 files: the plain FP32 vector path
              vs the BF16 table on the matrix cores (uint8 and FP8 features),
              with label agreement against the oracle on a sample.
+  groups     256 size groups with lognormal(7, 1.5) file counts in [100, 1e5],
+             F = 2000, each with its own two-class model: one persistent
+             launch per step replayed from a captured plan (autotuned tile)
+             vs one nb_score launch per group.
+  serve      continuous batching of scan requests against 8 resident models
+             (F in {500, 1000, 5000}), request sizes log-uniform on 1..4096,
+             Poisson arrivals: saturation throughput, then p50/p99 latency at
+             fractions of it, with host-resident (pinned) and device-resident
+             inputs.
 --copy-calibration runs only a plain device copy of known size (used to scale
 the HBM byte counters of rocprofv3).
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -80,14 +88,19 @@ def probe_bandwidth(nbg, gib: float = 4.0, reps: int = 20) -> float:
     return nbytes / (ms / 1e3) / 1e9
 
 
+# the files the two-class scoring kernel is compiled from
+SCORE2_SOURCES = ["paper_1905_13746_amd/csrc/nb_score.hip", "paper_1905_13746_amd/csrc/nb_score2.hpp",
+                  "paper_1905_13746_amd/csrc/nb_device.hpp"]
+
+
 def load_traffic(path):
     """HBM bytes per scoring launch from the committed rocprofv3 counter runs,
     if they were taken on the current scoring kernel source (hash match)."""
+    from paper_1905_13746_amd.rocprof_summary import source_hash
     try:
         with open(path) as fh:
             t = json.load(fh)
-        src = os.path.join(ROOT, "paper_1905_13746_amd", "csrc", "nb_score.hip")
-        if t.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        if t.get("sources") != SCORE2_SOURCES or t.get("source_sha256") != source_hash(SCORE2_SOURCES):
             return None
         return float(t["hbm_bytes_per_launch"])
     except Exception:
@@ -181,6 +194,98 @@ def precision_compare(nbg, W):
     res["speedup_bf16_u8_vs_fp32"] = res["fp32_vector"]["ms"] / res["bf16_mfma_u8"]["ms"]
     res["speedup_bf16_fp8_vs_fp32"] = res["fp32_vector"]["ms"] / res["bf16_mfma_fp8"]["ms"]
     return res
+
+
+def groups_leg(nbg, W, steps: int = 20):
+    """Batched size-group scoring (256 groups, F = 2000, two classes, FP32
+    table): a captured plan (one persistent launch) vs a loop of per-group
+    launches over the same buffers."""
+    sizes = W.group_sizes()
+    F = 2000
+    models, xs = [], []
+    for g, n in enumerate(sizes):
+        wl = W.group_workload(g, F)
+        X, y = wl.train_set(int(min(2 * n, 20_000)), device="cuda")
+        m = nbg.Model(2, F, "multinomial")
+        nbg.train(m, X, y)
+        del X, y
+        models.append(m)
+        xs.append(wl.test_set(int(n), device="cuda")[0])
+    groups = list(enumerate(xs))
+    plan = nbg.GroupPlan(models, groups, tune=True)
+    info = plan.info()
+    ms_plan = timed(plan.launch, steps)
+    outs = plan.outs
+
+    def loop():
+        for g, x in groups:
+            nbg.score(models[g], x, out=outs[g])
+
+    ms_loop = timed(loop, max(3, steps // 4))
+    n = int(sizes.sum())
+    algo = n * (F + 4 + 2 * 4)
+    gbs = algo / (ms_plan / 1e3) / 1e9
+    res = {"workload": f"256 groups, n_g = clip(round(lognormal(7, 1.5)), 100, 1e5), F={F} uint8, two classes, "
+                       "multinomial, FP32 table; models trained on min(2 n_g, 20000) files per group",
+           "n_files": n, "plan": info, "ms_per_launch": ms_plan, "files_per_s": n / (ms_plan / 1e3),
+           "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBPS,
+           "per_group_launch_loop_ms": ms_loop, "speedup_vs_loop": ms_loop / ms_plan}
+    plan.close()
+    return res
+
+
+def serve_leg(nbg, W, n_requests: int = 8000):
+    """Continuous-batching server on the 8-model request mix."""
+    models, pools_h, pools_d = [], [], []
+    for m in range(8):
+        wl = W.serve_model_workload(m)
+        X, y = wl.train_set(20_000, device="cuda")
+        mod = nbg.Model(2, wl.n_features, "multinomial")
+        nbg.train(mod, X, y)
+        del X, y
+        models.append(mod)
+        xd = wl.test_set(4096, device="cuda")[0]
+        pools_d.append(xd)
+        pools_h.append(xd.cpu().pin_memory())
+    arena = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    max_n = int(W.serve_requests(n_requests, 1.0)[0].sum())    # sizes do not depend on the rate
+    lab_pool = torch.empty(max_n, dtype=torch.int32).pin_memory()
+    lp_pool = torch.empty((max_n, 2), dtype=torch.float32).pin_memory()
+
+    def trace(qps):
+        sizes, mids, arr = W.serve_requests(n_requests, qps)
+        if qps == float("inf"):
+            arr = np.zeros_like(arr)
+        return sizes, mids, arr
+
+    def run(sizes, mids, arr, device_inputs):
+        reqs, off = [], 0
+        for n, m, t in zip(sizes, mids, arr):
+            n, m = int(n), int(m)
+            pool = pools_d[m] if device_inputs else pools_h[m]
+            reqs.append({"model": m, "arrival_s": float(t), "x": pool[:n],
+                         "labels": lab_pool[off:off + n], "log_post": lp_pool[off:off + n]})
+            off += n
+        torch.cuda.synchronize()
+        st, _ = nbg.serve(models, reqs, arena, n_streams=4, max_batch_requests=64, device_inputs=device_inputs)
+        return {"p50_ms": st["p50_s"] * 1e3, "p99_ms": st["p99_s"] * 1e3, "files_per_s": st["files_per_s"],
+                "req_per_s": st["served"] / st["makespan_s"] if st["makespan_s"] > 0 else None,
+                "input_GBps": st["bytes_per_s"] / 1e9, "batches": st["batches"], "rejected": st["rejected"]}
+
+    out = {"workload": f"{n_requests} requests per point; 8 models F={list(W.SERVE_F)}, two classes, uint8; "
+                       "n = floor(exp(U(0, ln 4097))); models uniform; Poisson arrivals; latency = arrival -> "
+                       "labels and log posteriors in pinned host memory; 4 streams, <= 64 requests per batch, "
+                       "1 GiB arena"}
+    for mode, dev in (("host_inputs", False), ("device_inputs", True)):
+        sat = run(*trace(float("inf")), dev)
+        res = {"saturation": sat}
+        for frac in (0.25, 0.5, 0.9):
+            qps = frac * sat["req_per_s"]
+            r = run(*trace(qps), dev)
+            r["offered_req_per_s"] = qps
+            res[f"load_{frac}"] = r
+        out[mode] = res
+    return out
 
 
 def copy_calibration():
@@ -290,6 +395,10 @@ def main():
         torch.cuda.empty_cache()
         rec["f_sweep"] = f_sweep(nbg, W)
         rec["precision"] = precision_compare(nbg, W)
+        torch.cuda.empty_cache()
+        rec["groups"] = groups_leg(nbg, W)
+        torch.cuda.empty_cache()
+        rec["serve"] = serve_leg(nbg, W)
         rec["paper_context"] = ("the paper reports up to 200x GPU over a sequential CPU program on a GTX 1050 Ti "
                                 "vs an i7-7700HQ, overheads excluded (section 4); different hardware and workload")
     print(json.dumps(rec), flush=True)

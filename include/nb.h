@@ -164,6 +164,147 @@ int nb_quantize_fp8(const uint8_t* x, int64_t n, int32_t n_features, int64_t ld_
 int nb_route_groups(const int64_t* class_counts_host, int32_t n_groups, int32_t n_classes,
                     int32_t min_files, int32_t* route_host);
 
+/* ------------------------------------------------- batched size groups
+ * Sections 3-4: the files are split into size groups and each group is
+ * classified by its own two-class model (benign / malware); a group without
+ * a model is classified with the model of the next group that has one (the
+ * first such group after it in `groups`, else the nearest one before it:
+ * the rule of nb_route_groups).  Every group of a call is scored by ONE
+ * persistent kernel launch over (group, tile) work items; each file's
+ * results are bit-identical to nb_score of its group alone (same summation
+ * order), whatever the tile, the grid or the other groups.
+ *
+ * One group of files (device pointers as for nb_score): */
+typedef struct {
+  int32_t     model;     /* index into models[], or -1: no model of its own   */
+  int32_t     reserved;  /* must be 0                                          */
+  const void* x;         /* [n x F] features of the call's xtype, stride ld   */
+  int64_t     n;         /* files of the group, >= 0 (0: skipped)             */
+  int64_t     ld;        /* row stride in elements, >= F                       */
+  int32_t*    labels;    /* int32[n]      or NULL                              */
+  float*      log_post;  /* float[n x 2]  or NULL (8-byte aligned)             */
+  float*      scores;    /* float[n x 2]  or NULL (8-byte aligned)             */
+} nb_group;
+
+/* Requirements: every model a group uses has two classes, and all of them
+ * share the kind and the feature count F (the paper keeps k features per
+ * group).  Each non-empty group needs at least one output.
+ * tile_rows: files per work item (rounded up to whole blocks of the kernel);
+ * 0 picks about four items per resident workgroup.
+ * Errors: NB_EINVAL (arguments, per group), NB_ENOMODEL (every model is -1),
+ * NB_ENOMEM (workspace too small), NB_EHIP. */
+
+/* Device workspace for nb_score_groups with these arguments (0 on error). */
+size_t nb_score_groups_workspace_bytes(const nb_model* models, int32_t n_models, const nb_group* groups,
+                                       int32_t n_groups, int32_t xtype, int32_t wtype, int32_t tile_rows);
+/* Build the work list, copy it into `workspace` (256-byte aligned, caller
+ * owned) and launch.  Returns after `stream` has completed the launch (the
+ * work list is staged from host memory); use a plan for repeated scoring. */
+int nb_score_groups(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
+                    int32_t xtype, int32_t wtype, int32_t tile_rows, void* workspace, size_t workspace_bytes,
+                    void* stream);
+
+/* A plan fixes one grouped call (models, groups, buffers, types) and holds
+ * its work list in device memory plus a HIP graph of the launch: each
+ * nb_group_plan_launch replays the graph (one kernel node, no memset; the
+ * kernel re-arms its own work counter), so new data written into the same
+ * input buffers is scored with no host work.  Creation allocates device
+ * memory (hipMalloc) and synchronises `stream`; launching allocates nothing.
+ * Launches of one plan must not overlap (they share the work counter).
+ * Tile choice (tile_rows == 0): a tile recorded for the same shape (kept in
+ * memory, and in the JSON file named by the NB_TUNE_CACHE environment
+ * variable when set), else with NB_PLAN_TUNE the fastest of several tiles
+ * timed on the caller's data (this scores the groups, writing the outputs,
+ * a few times), else the default above. */
+typedef struct nb_group_plan nb_group_plan;
+#define NB_PLAN_TUNE 1
+
+typedef struct {
+  int32_t tile_rows;       /* files per full work item                         */
+  int32_t n_items;         /* work items of one launch                         */
+  int32_t grid;            /* workgroups launched                              */
+  int32_t tuned;           /* 0 default or caller's tile, 1 timed, 2 cached    */
+  int64_t n_files;         /* files scored per launch                          */
+  int32_t rows_per_block;  /* files per wave block of the kernel               */
+  int32_t lds_bytes;       /* table bytes staged in LDS per workgroup          */
+  int32_t reserved;
+} nb_group_plan_info;
+
+int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
+                         int32_t xtype, int32_t wtype, int32_t tile_rows, int32_t flags, void* stream,
+                         nb_group_plan** out);
+int nb_group_plan_launch(nb_group_plan* plan, void* stream);
+int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out);
+/* Waits for the device, then frees the plan (NULL is a no-op). */
+int nb_group_plan_destroy(nb_group_plan* plan);
+
+/* ---------------------------------------------------------------- serving
+ * Section 4's classifier behind a request queue: scan requests (a batch of
+ * files for one resident two-class model) are served by continuous
+ * batching.  nb_serve replays a request trace in real time: request i joins
+ * the queue arrival_s seconds after the call starts.  Whenever fewer than
+ * n_streams batches are in flight, the queue's head requests (arrival
+ * order, no overtaking) are admitted while their device footprint fits the
+ * arena (first fit; inputs when host resident, labels, log posteriors) and
+ * up to max_batch_requests of them form a batch: host-to-device copies, one
+ * persistent grouped launch per feature count present (the kernel of
+ * nb_score_groups: each request is a group with its own model), device-to-
+ * host copies of the outputs, all on one stream of the batch.  A finished
+ * batch frees its arena space.  A request whose footprint exceeds the whole
+ * arena is rejected (status NB_EREJECTED); the others proceed.  Outputs are
+ * identical to nb_score of the request alone.
+ * Requests: */
+typedef struct {
+  int32_t     model;          /* index into models[]                              */
+  int32_t     status;         /* out: NB_OK or NB_EREJECTED (or NB_E* on failure) */
+  const void* x;              /* [n x F] features of cfg.xtype, rows contiguous;
+                                 host memory (pinned, for asynchronous copies),
+                                 or device memory with NB_SERVE_DEVICE_INPUTS     */
+  int64_t     n;              /* files, >= 1                                      */
+  double      arrival_s;      /* seconds after the start of the call, >= 0        */
+  int32_t*    labels_host;    /* out: int32[n] (host, pinned) or NULL             */
+  float*      log_post_host;  /* out: float[n x 2] (host, pinned) or NULL         */
+  double      done_s;         /* out: seconds after the start when the outputs were
+                                 observed in host memory (or the rejection)       */
+} nb_request;
+
+#define NB_SERVE_DEVICE_INPUTS 1  /* request x pointers are device memory        */
+#define NB_SERVE_SIMULATE      2  /* no device work: each batch completes after
+                                     sim_batch_s + bytes / sim_bytes_per_s; for
+                                     testing the scheduler and for capacity
+                                     planning (models need no device buffers)     */
+
+typedef struct {
+  void*   arena;              /* device memory, 256-byte aligned, caller owned   */
+  size_t  arena_bytes;
+  int32_t max_batch_requests; /* >= 1                                             */
+  int32_t n_streams;          /* batches in flight, 1 .. 16                       */
+  int32_t xtype;              /* feature type of every request                    */
+  int32_t wtype;              /* scoring table type                               */
+  int32_t flags;              /* NB_SERVE_* flags                                 */
+  int32_t reserved;           /* must be 0                                        */
+  double  sim_batch_s;        /* NB_SERVE_SIMULATE: fixed time per batch          */
+  double  sim_bytes_per_s;    /* NB_SERVE_SIMULATE: feature bytes per second      */
+} nb_serve_cfg;
+
+typedef struct {
+  double  p50_s, p99_s;       /* latency arrival -> outputs in host memory,       */
+  double  mean_s, max_s;      /*   over served requests                           */
+  double  makespan_s;         /* first arrival -> last completion                 */
+  double  files_per_s;        /* served files / makespan                          */
+  double  bytes_per_s;        /* served feature bytes / makespan                  */
+  int64_t served, rejected, batches;
+  int64_t peak_arena_bytes;   /* largest arena footprint in use at once           */
+  int32_t max_in_flight;      /* most batches in flight at once                   */
+  int32_t reserved;
+} nb_serve_stats;
+
+/* Blocks until every request is served or rejected.  Models: two classes,
+ * any mix of feature counts and kinds.  Errors: NB_EINVAL (arguments, checked
+ * for every request before the trace starts), NB_EHIP. */
+int nb_serve(const nb_model* models, int32_t n_models, nb_request* requests, int64_t n_requests,
+             const nb_serve_cfg* cfg, nb_serve_stats* stats);
+
 /* ---------------------------------------------------------------- probe
  * Read-only streaming kernel used to measure achievable HBM bandwidth:
  * reads `bytes` bytes (multiple of 16) at `src` and writes one uint32 per

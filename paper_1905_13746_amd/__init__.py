@@ -179,3 +179,144 @@ def probe_read(buf: torch.Tensor, sink: torch.Tensor | None = None, stream=None)
     check(lib.nb_probe_read(_ptr(buf), buf.numel() * buf.element_size(), _ptr(sink), _stream(stream)),
           "nb_probe_read")
     return sink
+
+
+class _GroupCall:
+    """Marshalling of a grouped call: the models array, one nb_group per group
+    and its output tensors (allocated here unless given)."""
+
+    def __init__(self, models, groups, fp8=False, labels=True, log_post=True, scores=False, outs=None):
+        if not models or not groups:
+            raise ValueError("need at least one model and one group")
+        self.models = list(models)
+        self.cmodels = (_lib.NbModel * len(self.models))(*[m.c for m in self.models])
+        self.xs, self.outs = [], []
+        self.cgroups = (_lib.NbGroup * len(groups))()
+        self.xtype = None
+        for i, (mi, x) in enumerate(groups):
+            n, F, ld = _rows(x)
+            xt = xtype_of(x, fp8)
+            if self.xtype is None:
+                self.xtype = xt
+            elif xt != self.xtype:
+                raise TypeError("all groups must share one feature type")
+            if outs is not None:
+                lab, lp, sc = outs[i]
+            else:
+                dev = x.device
+                lab = torch.empty(n, dtype=torch.int32, device=dev) if labels else None
+                lp = torch.empty((n, 2), dtype=torch.float32, device=dev) if log_post else None
+                sc = torch.empty((n, 2), dtype=torch.float32, device=dev) if scores else None
+            self.xs.append(x)
+            self.outs.append((lab, lp, sc))
+            g = self.cgroups[i]
+            g.model = -1 if mi is None else int(mi)
+            g.reserved = 0
+            g.x = x.data_ptr() if n > 0 else None
+            g.n, g.ld = n, ld
+            g.labels = None if lab is None else lab.data_ptr()
+            g.log_post = None if lp is None else lp.data_ptr()
+            g.scores = None if sc is None else sc.data_ptr()
+
+    def args(self):
+        return self.cmodels, len(self.models), self.cgroups, len(self.cgroups), self.xtype
+
+
+def score_groups(models, groups, wtype: int = W_F32, fp8: bool = False, labels=True, log_post=True, scores=False,
+                 tile_rows: int = 0, outs=None, stream=None):
+    """Score size groups in one launch.  groups: [(model index or None, x [n, F])]
+    (None: no model of its own; the next group's model is used).  Returns the
+    per-group (labels, log_post, scores) outputs."""
+    lib = load()
+    call = _GroupCall(models, groups, fp8, labels, log_post, scores, outs)
+    cm, nm, cg, ng, xt = call.args()
+    ws_bytes = lib.nb_score_groups_workspace_bytes(cm, nm, cg, ng, xt, int(wtype), int(tile_rows))
+    if ws_bytes == 0:   # invalid arguments: the call itself reports which
+        check(lib.nb_score_groups(cm, nm, cg, ng, xt, int(wtype), int(tile_rows), None, 0, _stream(stream)),
+              "nb_score_groups")
+        return call.outs    # nothing to score
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=call.xs[0].device)
+    check(lib.nb_score_groups(cm, nm, cg, ng, xt, int(wtype), int(tile_rows), _ptr(ws), ws_bytes, _stream(stream)),
+          "nb_score_groups")
+    return call.outs
+
+
+class GroupPlan:
+    """A fixed grouped call captured once (work list on the device, HIP graph
+    of the one persistent launch); launch() replays it."""
+
+    def __init__(self, models, groups, wtype: int = W_F32, fp8: bool = False, labels=True, log_post=True,
+                 scores=False, tile_rows: int = 0, tune: bool = False, outs=None, stream=None):
+        lib = load()
+        self._lib = lib
+        self.call = _GroupCall(models, groups, fp8, labels, log_post, scores, outs)
+        cm, nm, cg, ng, xt = self.call.args()
+        h = ctypes.c_void_p()
+        check(lib.nb_group_plan_create(cm, nm, cg, ng, xt, int(wtype), int(tile_rows),
+                                       _lib.PLAN_TUNE if tune else 0, _stream(stream), ctypes.byref(h)),
+              "nb_group_plan_create")
+        self.handle = h
+
+    @property
+    def outs(self):
+        return self.call.outs
+
+    def launch(self, stream=None):
+        check(self._lib.nb_group_plan_launch(self.handle, _stream(stream)), "nb_group_plan_launch")
+
+    def info(self) -> dict:
+        inf = _lib.NbGroupPlanInfo()
+        check(self._lib.nb_group_plan_query(self.handle, ctypes.byref(inf)), "nb_group_plan_query")
+        return {k: getattr(inf, k) for k, _ in inf._fields_ if k != "reserved"}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check(self._lib.nb_group_plan_destroy(self.handle), "nb_group_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve(models, requests, arena: torch.Tensor | None = None, arena_bytes: int = 0, max_batch_requests: int = 64,
+          n_streams: int = 4, xtype: int = X_U8, wtype: int = W_F32, device_inputs: bool = False,
+          simulate: tuple | None = None):
+    """Replay a request trace through the continuous-batching server.
+
+    requests: list of dicts {model, x (tensor [n, F]; host, ideally pinned,
+    or device with device_inputs), arrival_s, labels (int32[n] host tensor or
+    None), log_post (float32[n, 2] host tensor or None)}.  The arena is a
+    device uint8 tensor (or arena_bytes with simulate=(batch_s, bytes_per_s),
+    which runs the scheduler with modelled batch times and no device work).
+    Returns (stats dict, [(status, done_s)] per request)."""
+    lib = load()
+    creq = (_lib.NbRequest * len(requests))()
+    keep = []
+    for i, r in enumerate(requests):
+        q = creq[i]
+        q.model = int(r["model"])
+        x = r.get("x")
+        q.x = None if x is None else x.data_ptr()
+        q.n = int(r["n"]) if x is None else x.shape[0]
+        q.arrival_s = float(r["arrival_s"])
+        lab, lp = r.get("labels"), r.get("log_post")
+        q.labels_host = None if lab is None else lab.data_ptr()
+        q.log_post_host = None if lp is None else lp.data_ptr()
+        keep.append((x, lab, lp))
+    cfg = _lib.NbServeCfg()
+    if simulate is not None:
+        cfg.arena, cfg.arena_bytes = None, int(arena_bytes)
+        cfg.sim_batch_s, cfg.sim_bytes_per_s = float(simulate[0]), float(simulate[1])
+    else:
+        cfg.arena, cfg.arena_bytes = arena.data_ptr(), arena.numel() * arena.element_size()
+    cfg.max_batch_requests, cfg.n_streams = int(max_batch_requests), int(n_streams)
+    cfg.xtype, cfg.wtype = int(xtype), int(wtype)
+    cfg.flags = (_lib.SERVE_DEVICE_INPUTS if device_inputs else 0) | (_lib.SERVE_SIMULATE if simulate else 0)
+    cmodels = (_lib.NbModel * len(models))(*[m.c if hasattr(m, "c") else m for m in models])
+    st = _lib.NbServeStats()
+    check(lib.nb_serve(cmodels, len(models), creq, len(requests), ctypes.byref(cfg), ctypes.byref(st)), "nb_serve")
+    stats = {k: getattr(st, k) for k, _ in st._fields_ if k != "reserved"}
+    return stats, [(creq[i].status, creq[i].done_s) for i in range(len(requests))]

@@ -20,6 +20,8 @@ MULTINOMIAL, BERNOULLI = 0, 1
 X_U8, X_I32, X_FP8 = 0, 1, 2
 W_F32, W_BF16 = 0, 1
 TRAIN_ASYNC = 1
+PLAN_TUNE = 1
+SERVE_DEVICE_INPUTS, SERVE_SIMULATE = 1, 2
 
 
 class NbModel(ctypes.Structure):
@@ -39,8 +41,43 @@ class NbLayout(ctypes.Structure):
                 ("off_form_bias", ctypes.c_size_t), ("alpha", ctypes.c_double)]
 
 
+class NbGroup(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("reserved", ctypes.c_int32), ("x", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("labels", ctypes.c_void_p),
+                ("log_post", ctypes.c_void_p), ("scores", ctypes.c_void_p)]
+
+
+class NbGroupPlanInfo(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("n_items", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("tuned", ctypes.c_int32), ("n_files", ctypes.c_int64), ("rows_per_block", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class NbRequest(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("status", ctypes.c_int32), ("x", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("arrival_s", ctypes.c_double), ("labels_host", ctypes.c_void_p),
+                ("log_post_host", ctypes.c_void_p), ("done_s", ctypes.c_double)]
+
+
+class NbServeCfg(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("max_batch_requests", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("xtype", ctypes.c_int32), ("wtype", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("sim_batch_s", ctypes.c_double),
+                ("sim_bytes_per_s", ctypes.c_double)]
+
+
+class NbServeStats(ctypes.Structure):
+    _fields_ = [("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("makespan_s", ctypes.c_double), ("files_per_s", ctypes.c_double),
+                ("bytes_per_s", ctypes.c_double), ("served", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("peak_arena_bytes", ctypes.c_int64),
+                ("max_in_flight", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _i32, _i64, _sz, _vp, _d = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 _PM = ctypes.POINTER(NbModel)
+_PG = ctypes.POINTER(NbGroup)
 
 # name -> (restype, argtypes); every symbol include/nb.h declares
 SIGNATURES = {
@@ -54,6 +91,15 @@ SIGNATURES = {
     "nb_score": (ctypes.c_int, [_PM, _vp, _i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp]),
     "nb_quantize_fp8": (ctypes.c_int, [_vp, _i64, _i32, _i64, _vp, _i64, _vp]),
     "nb_route_groups": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp]),
+    "nb_score_groups_workspace_bytes": (_sz, [_PM, _i32, _PG, _i32, _i32, _i32, _i32]),
+    "nb_score_groups": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _vp, _sz, _vp]),
+    "nb_group_plan_create": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _i32, _vp,
+                                            ctypes.POINTER(_vp)]),
+    "nb_group_plan_launch": (ctypes.c_int, [_vp, _vp]),
+    "nb_group_plan_query": (ctypes.c_int, [_vp, ctypes.POINTER(NbGroupPlanInfo)]),
+    "nb_group_plan_destroy": (ctypes.c_int, [_vp]),
+    "nb_serve": (ctypes.c_int, [_PM, _i32, ctypes.POINTER(NbRequest), _i64, ctypes.POINTER(NbServeCfg),
+                                ctypes.POINTER(NbServeStats)]),
     "nb_probe_sink_words": (_i32, []),
     "nb_probe_read": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
 }

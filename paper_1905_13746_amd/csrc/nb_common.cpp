@@ -2,7 +2,9 @@
 // routing and the version string.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -90,6 +92,33 @@ int device_cu_count() {
   return cache[dev];
 }
 
+void route_trained(const char* trained, int32_t n_groups, int32_t* route) {
+  // next trained group above; scan from the top so each lookup is O(1)
+  int32_t next = -1;
+  for (int32_t g = n_groups - 1; g >= 0; --g) {
+    if (trained[g]) next = g;
+    route[g] = next;
+  }
+  int32_t prev = -1;
+  for (int32_t g = 0; g < n_groups; ++g) {
+    if (trained[g]) prev = g;
+    if (route[g] < 0) route[g] = prev;   // none above: nearest below
+  }
+}
+
+int resident_per_cu(const void* fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, size_t>, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_tuple(fn, threads, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, lds) != hipSuccess || per < 1) per = 1;
+  cache[key] = per;
+  return per;
+}
+
 }  // namespace nb
 
 extern "C" {
@@ -126,17 +155,7 @@ int nb_route_groups(const int64_t* class_counts_host, int32_t n_groups, int32_t 
     any = any || trained[g];
   }
   if (!any) return nb::fail(NB_ENOMODEL, "no size group has enough files in every class");
-  // next trained group above; scan from the top so each lookup is O(1)
-  int32_t next = -1;
-  for (int32_t g = n_groups - 1; g >= 0; --g) {
-    if (trained[g]) next = g;
-    route_host[g] = next;
-  }
-  int32_t prev = -1;
-  for (int32_t g = 0; g < n_groups; ++g) {
-    if (trained[g]) prev = g;
-    if (route_host[g] < 0) route_host[g] = prev;   // none above: nearest below
-  }
+  nb::route_trained(trained.data(), n_groups, route_host);
   return NB_OK;
 }
 

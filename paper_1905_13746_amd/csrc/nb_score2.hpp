@@ -1,0 +1,464 @@
+// Two-class scoring building blocks shared by the single-model kernel
+// (nb_score.hip) and the grouped persistent kernel (nb_groups.hip).
+//
+// A row (file) is split across LPR lanes of a wave (LPR = the smallest power
+// of two >= F/16, at most 64), each lane owning 16 consecutive features per
+// chunk of 16*LPR features.  A wave processes blocks of R row-steps of
+// 64/LPR rows; the table rows sit in LDS as FP32.  See nb_score.hip for the
+// full description of the mapping and of the summation order.
+#pragma once
+
+#include <algorithm>
+
+#include "nb_device.hpp"
+#include "nb_internal.hpp"
+
+namespace nb {
+namespace {
+
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+// Rows per lane group per block, and whether a wave double-buffers its loads
+// (the next unit's loads in flight while the current one is accumulated).
+#ifndef NB_ROW_STEPS
+#define NB_ROW_STEPS 8
+#endif
+#ifndef NB_PIPELINE
+#define NB_PIPELINE 1
+#endif
+constexpr int kRowSteps = NB_ROW_STEPS;
+constexpr bool kPipeline = NB_PIPELINE != 0;
+
+struct Score2Args {
+  const uint8_t* x;
+  int64_t ld_bytes;
+  int64_t n;
+  int64_t total_bytes;
+  const float* rows32;      // [2][Fp] log-odds row, aux row
+  const uint16_t* rows16;   // same rows in BF16
+  const float* row_bias;    // [2]
+  int32_t* labels;
+  float* log_post;
+  float* scores;
+  int64_t nfast;            // leading blocks with every row present and in bounds
+  int32_t F, Fp, nch, wt;
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Convert the 16 features of one lane's segment and accumulate them into
+// acc[s] against the 16 table values w[s][*].
+template <int XT, int NS, bool BIN>
+__device__ __forceinline__ void accumulate_seg(const dev::u32x4 (&v)[(XT == NB_X_I32) ? 4 : 1],
+                                               const float (&w)[NS][16], float (&acc)[NS]) {
+  float xf[16];
+  if (XT == NB_X_I32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) xf[4 * q + d] = (float)(int32_t)v[q][d];
+  } else if (XT == NB_X_U8) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t u = v[0][d];
+      xf[4 * d + 0] = (float)(u & 0xFFu);
+      xf[4 * d + 1] = (float)((u >> 8) & 0xFFu);
+      xf[4 * d + 2] = (float)((u >> 16) & 0xFFu);
+      xf[4 * d + 3] = (float)(u >> 24);
+    }
+  } else {  // FP8 e4m3
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t u = v[0][d];
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(u, false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(u, true);
+      xf[4 * d + 0] = lo[0];
+      xf[4 * d + 1] = lo[1];
+      xf[4 * d + 2] = hi[0];
+      xf[4 * d + 3] = hi[1];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    // presence: byte/int counts are integers >= 0, so min(x, 1) is 1[x > 0];
+    // FP8 values may be fractional, so compare
+    const float g = !BIN ? xf[e] : (XT == NB_X_FP8 ? (xf[e] > 0.0f ? 1.0f : 0.0f) : fminf(xf[e], 1.0f));
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = fmaf(g, w[s][e], acc[s]);
+  }
+}
+
+// Destination of outputs the caller did not request: the fast path stores
+// every output unconditionally so the number of memory operations in flight
+// is known at compile time (loads of the next unit stay in flight).
+__device__ int32_t g_sink_label[64];
+__device__ float2 g_sink_pair[64];
+
+// Reduce acc[R][NS] across the LPR lanes of each row group (transposed
+// butterfly), stage the per-row totals in LDS and run the fused epilogue for
+// the block's rows [row0, row0 + nrows).  FAST: nrows == BR and no branches
+// around the stores (lanes beyond BR repeat a row: same value, same address).
+template <int LPR, int NS, bool FAST>
+__device__ __forceinline__ void finish_block(const Score2Args& a, float (&acc)[kRowSteps][NS], int lane, int wave,
+                                             int sub, const float (&rb)[NS], int64_t row0, int nrows,
+                                             float (*stage)[NS][(64 / LPR) * kRowSteps]) {
+  constexpr int G = 64 / LPR;
+  constexpr int R = kRowSteps;
+  constexpr int BR = G * R;
+  constexpr int V = R * NS;
+  float val[V];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) val[i * NS + s] = acc[i][s];
+  int offset = 0;
+  bool owner = true;
+  int cnt = V;
+#pragma unroll
+  for (int m = LPR / 2; m >= 1; m >>= 1) {
+    const bool up = (lane & m) != 0;
+    if (cnt > 1) {
+      const int h = cnt / 2;
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const float send = up ? val[k] : val[k + h];
+        const float keep = up ? val[k + h] : val[k];
+        val[k] = keep + __shfl_xor(send, m);
+      }
+      if (up) offset += h;
+      cnt = h;
+    } else {
+      val[0] += __shfl_xor(val[0], m);
+      if (up) owner = false;
+    }
+  }
+  // cnt values remain per lane, value indices offset .. offset + cnt - 1
+  if (owner) {
+#pragma unroll
+    for (int k = 0; k < cnt; ++k) {
+      const int idx = offset + k;
+      stage[wave][idx % NS][(idx / NS) * G + sub] = val[k];
+    }
+  }
+  wave_lds_sync();
+  const bool want_lab = a.labels != nullptr, want_lp = a.log_post != nullptr, want_sc = a.scores != nullptr;
+#pragma unroll
+  for (int L0 = 0; L0 < BR; L0 += 64) {
+    const int L = (BR >= 64) ? L0 + lane : lane % BR;
+    if (FAST || L < nrows) {
+      const int64_t row = row0 + L;
+      const float delta = stage[wave][0][L] + rb[0];
+      // log(1 + e^-|delta|) with the hardware exp/log: absolute error ~1e-7
+      const float t = __logf(1.0f + __expf(-fabsf(delta)));
+      float2 lp;
+      lp.x = fminf(-delta, 0.0f) - t;
+      lp.y = fminf(delta, 0.0f) - t;
+      if (FAST) {
+        int32_t* pl = want_lab ? a.labels + row : g_sink_label + lane;
+        float2* pp = want_lp ? reinterpret_cast<float2*>(a.log_post) + row : g_sink_pair + lane;
+        *pl = delta > 0.0f ? 1 : 0;
+        *pp = lp;
+        if (NS == 2) {
+          float2 sc;
+          sc.x = stage[wave][NS - 1][L] + rb[NS - 1];
+          sc.y = sc.x + delta;
+          float2* ps = want_sc ? reinterpret_cast<float2*>(a.scores) + row : g_sink_pair + lane;
+          *ps = sc;
+        }
+      } else {
+        if (want_lab) a.labels[row] = delta > 0.0f ? 1 : 0;
+        if (want_lp) reinterpret_cast<float2*>(a.log_post)[row] = lp;
+        if (NS == 2 && want_sc) {
+          float2 sc;
+          sc.x = stage[wave][NS - 1][L] + rb[NS - 1];
+          sc.y = sc.x + delta;
+          reinterpret_cast<float2*>(a.scores)[row] = sc;
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
+template <int XT, int NS>
+__device__ __forceinline__ void load_table(const float* tbl, int Fp, int fc, float (&w)[NS][16]) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const float4* t4 = reinterpret_cast<const float4*>(tbl + s * Fp + fc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = t4[q];
+      w[s][4 * q + 0] = t.x;
+      w[s][4 * q + 1] = t.y;
+      w[s][4 * q + 2] = t.z;
+      w[s][4 * q + 3] = t.w;
+    }
+  }
+}
+
+// FP8 bytes past the last feature may hold NaN encodings: mask them.
+__device__ __forceinline__ void fp8_keep_mask(int F, int fc, uint32_t (&keep)[4]) {
+  const int nv = max(0, F - fc);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int nb = min(4, max(0, nv - 4 * d));
+    keep[d] = (nb >= 4) ? ~0u : ((1u << (8 * nb)) - 1u);
+  }
+}
+
+template <int XT, int NS, bool BIN, int NV>
+__device__ __forceinline__ void accumulate_rows(dev::u32x4 (&v)[kRowSteps][NV], const float (&w)[NS][16],
+                                                const uint32_t (&keep)[4], bool masked,
+                                                float (&acc)[kRowSteps][NS]) {
+#pragma unroll
+  for (int i = 0; i < kRowSteps; ++i) {
+    if (XT == NB_X_FP8 && masked) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[i][0][d] &= keep[d];
+    }
+    accumulate_seg<XT, NS, BIN>(v[i], w, acc[i]);
+  }
+}
+
+
+// Copy the NS scoring rows (FP32, or BF16 widened: exact) into LDS.  The
+// caller synchronises the workgroup afterwards.
+template <int NS>
+__device__ __forceinline__ void stage_table(const Score2Args& a, float* tbl) {
+  for (int i = threadIdx.x; i < NS * a.Fp; i += kThreads)
+    tbl[i] = (a.wt == NB_W_BF16) ? dev::bf16_to_f32(a.rows16[i]) : a.rows32[i];
+}
+
+// One wave scores the blocks first, first + stride, ... below `end` of the
+// files described by `a` (a block is R row-steps of 64/LPR rows; rows are
+// relative to a.x and to the output pointers).  Blocks below a.nfast take
+// the pipelined path: every row present and every load in bounds, the loads
+// of the next unit (block, chunk) in flight while the current one is
+// accumulated.  The rest take guarded loads.  tbl: the rows in LDS.
+// MULTI: F spans more than one chunk of 16*LPR features (only with LPR = 64).
+template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+__device__ __forceinline__ void score_blocks(const Score2Args& a, const float* tbl, int64_t first, int64_t stride,
+                                             int64_t end, float (*stage)[NS][(64 / LPR) * kRowSteps]) {
+  constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
+  constexpr int NV = EB;
+  constexpr int G = 64 / LPR;           // rows per row-step
+  constexpr int R = kRowSteps;
+  constexpr int BR = G * R;             // rows per block
+  constexpr int CW = 16 * LPR;          // features per chunk
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sub = lane / LPR, j = lane % LPR;
+  const int nch = MULTI ? a.nch : 1;
+  const int64_t ld = a.ld_bytes;
+  // this lane's byte offsets inside a block: row (i*G + sub), feature 16*j
+  uint32_t voff[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) voff[i] = (uint32_t)((i * G + sub) * ld) + (uint32_t)(16 * j * EB);
+
+  float rb[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rb[s] = a.row_bias[s];
+
+  float w[NS][16];
+  uint32_t keep[4] = {~0u, ~0u, ~0u, ~0u};
+  if (!MULTI) {
+    load_table<XT, NS>(tbl, a.Fp, 16 * j, w);
+    if (XT == NB_X_FP8) fp8_keep_mask(a.F, 16 * j, keep);
+  }
+
+  float acc[R][NS];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+
+  // ---- fast blocks: first + i*stride < min(end, nfast).  Per-wave counters
+  // are 32-bit so loop control stays on the scalar unit.
+  const int64_t fast_end = a.nfast < end ? a.nfast : end;
+  const int my_blocks = (fast_end > first) ? (int)((fast_end - first + stride - 1) / stride) : 0;
+  const int units = my_blocks * nch;
+  dev::u32x4 buf0[R][NV], buf1[R][NV];
+  int ib = 0;       // index of the block being issued, among this wave's blocks
+  int ich = 0;      // chunk being issued
+  auto rewind = [&]() {          // point the issue cursor back at the last issued unit
+    if (ich == 0) {
+      ich = nch - 1;
+      --ib;
+    } else {
+      --ich;
+    }
+  };
+  auto issue = [&](dev::u32x4 (&dst)[R][NV]) {
+    const int64_t blk = first + (int64_t)ib * stride;
+    const int64_t off = blk * BR * ld + (int64_t)ich * CW * EB;
+    const auto rsrc = dev::make_rsrc(a.x + off, a.total_bytes - off);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, voff[i] + 16 * q);
+    // keep the loads here: the scheduler would otherwise sink them into the
+    // arithmetic of the unit being consumed and shrink the overlap
+    __builtin_amdgcn_sched_barrier(0);
+    if (++ich == nch) {
+      ich = 0;
+      ++ib;
+    }
+  };
+  int cb = 0;       // block being computed
+  int cch = 0;      // chunk being computed
+  auto consume = [&](dev::u32x4 (&src)[R][NV]) {
+    if (MULTI) {
+      const int fc = cch * CW + 16 * j;
+      load_table<XT, NS>(tbl, a.Fp, fc, w);
+      if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
+    }
+    accumulate_rows<XT, NS, BIN, NV>(src, w, keep, true, acc);
+    if (++cch == nch) {
+      finish_block<LPR, NS, true>(a, acc, lane, wave, sub, rb, (first + (int64_t)cb * stride) * BR, BR, stage);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+      cch = 0;
+      ++cb;
+    }
+  };
+  // The prefetch of the unit after the last one re-reads the last unit (an L2
+  // hit) so that every iteration issues the same loads unconditionally.
+  if (units > 0 && !kPipeline) {
+    for (int u = 0; u < units; ++u) {
+      issue(buf0);
+      consume(buf0);
+    }
+  } else if (units > 0) {
+    issue(buf0);
+    for (int u = 0;; u += 2) {
+      if (u + 1 >= units) rewind();
+      issue(buf1);
+      consume(buf0);
+      if (u + 1 >= units) break;
+      if (u + 2 >= units) rewind();
+      issue(buf0);
+      consume(buf1);
+      if (u + 2 >= units) break;
+    }
+  }
+
+  // ---- the wave's remaining blocks: guarded loads, partial rows
+  const int64_t nrows_total = a.n;
+  for (int64_t blk = first + (int64_t)my_blocks * stride; blk < end; blk += stride) {
+    const int64_t row0 = blk * BR;
+    const int nrows = (int)min((int64_t)BR, nrows_total - row0);
+    for (int ch = 0; ch < nch; ++ch) {
+      const int fc = ch * CW + 16 * j;
+      if (MULTI) {
+        load_table<XT, NS>(tbl, a.Fp, fc, w);
+        if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
+      }
+      dev::u32x4 v[R][NV];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int L = i * G + sub;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[i][q] = dev::u32x4{0u, 0u, 0u, 0u};
+        if (L < nrows) {
+          const int64_t off = (row0 + L) * ld + (int64_t)fc * EB;
+#pragma unroll
+          for (int q = 0; q < NV; ++q)
+            v[i][q] = dev::load16_guarded(a.x + off + 16 * q, a.total_bytes - off - 16 * q);
+        }
+      }
+      accumulate_rows<XT, NS, BIN, NV>(v, w, keep, true, acc);
+    }
+    finish_block<LPR, NS, false>(a, acc, lane, wave, sub, rb, row0, nrows, stage);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+  }
+}
+
+// ------------------------------------------------------------ host helpers
+int lanes_per_row(int F) {
+  const int need = (F + 15) / 16;
+  int l = 4;
+  while (l < need && l < 64) l <<= 1;
+  return l;
+}
+
+constexpr size_t kMaxTableLds = 128 * 1024;
+
+// Launch arguments of the two-class kernels for one model and one feature
+// matrix (arguments already validated).  Returns NB_OK or NB_EINVAL.
+int make_score2_args(const nb_model* m, const nb_layout& L, const void* x, int32_t xtype, int64_t n, int64_t ld,
+                     int32_t wtype, int32_t* labels, float* log_post, float* scores, int ns, Score2Args* out) {
+  const int F = m->n_features;
+  const int eb = elem_bytes(xtype);
+  const int lpr = lanes_per_row(F);
+  const int cw = 16 * lpr;
+  const int nch = (F + cw - 1) / cw;
+  if ((size_t)ns * L.padded_features * sizeof(float) > kMaxTableLds)
+    return fail(NB_EINVAL, "two-class scoring supports F up to 16384 (table staged in LDS)");
+  const uint8_t* base = static_cast<const uint8_t*>(m->dev);
+  Score2Args a;
+  a.x = static_cast<const uint8_t*>(x);
+  a.ld_bytes = ld * eb;
+  a.n = n;
+  a.total_bytes = ((n - 1) * ld + F) * (int64_t)eb;
+  a.rows32 = reinterpret_cast<const float*>(base + L.off_form_f32);
+  a.rows16 = reinterpret_cast<const uint16_t*>(base + L.off_form_bf16);
+  a.row_bias = reinterpret_cast<const float*>(base + L.off_form_bias);
+  a.labels = labels;
+  a.log_post = log_post;
+  a.scores = scores;
+  a.F = F;
+  a.Fp = L.padded_features;
+  a.nch = nch;
+  a.wt = wtype;
+  const int64_t rows_per_blk = (int64_t)(64 / lpr) * kRowSteps;
+  if (rows_per_blk * a.ld_bytes >= (int64_t)1 << 31)
+    return fail(NB_EINVAL, "row stride too large (a block of rows must span < 2 GiB)");
+  // leading blocks whose rows all exist and whose loads stay inside the buffer
+  const int64_t span = (int64_t)nch * cw * eb;
+  const int64_t full = n / rows_per_blk;
+  const int64_t rmax = (a.total_bytes >= span) ? (a.total_bytes - span) / a.ld_bytes : -1;
+  a.nfast = std::max<int64_t>(0, std::min(full, (rmax + 1) / rows_per_blk));
+  *out = a;
+  return NB_OK;
+}
+
+// Kernel pointer of a two-class kernel family: Fam::fn<XT, LPR, NS, BIN, MULTI>().
+template <class Fam, int XT, int NS, bool BIN>
+const void* pick_lpr(int lpr, bool multi) {
+  switch (lpr) {
+    case 4: return Fam::template fn<XT, 4, NS, BIN, false>();
+    case 8: return Fam::template fn<XT, 8, NS, BIN, false>();
+    case 16: return Fam::template fn<XT, 16, NS, BIN, false>();
+    case 32: return Fam::template fn<XT, 32, NS, BIN, false>();
+    default: return multi ? Fam::template fn<XT, 64, NS, BIN, true>() : Fam::template fn<XT, 64, NS, BIN, false>();
+  }
+}
+
+template <class Fam, int XT>
+const void* pick_ns_bin(int lpr, bool multi, int ns, bool bin) {
+  if (ns == 1) return bin ? pick_lpr<Fam, XT, 1, true>(lpr, multi) : pick_lpr<Fam, XT, 1, false>(lpr, multi);
+  return bin ? pick_lpr<Fam, XT, 2, true>(lpr, multi) : pick_lpr<Fam, XT, 2, false>(lpr, multi);
+}
+
+template <class Fam>
+const void* pick_score2(int xtype, int lpr, bool multi, int ns, bool bin) {
+  switch (xtype) {
+    case NB_X_U8: return pick_ns_bin<Fam, NB_X_U8>(lpr, multi, ns, bin);
+    case NB_X_I32: return pick_ns_bin<Fam, NB_X_I32>(lpr, multi, ns, bin);
+    default: return pick_ns_bin<Fam, NB_X_FP8>(lpr, multi, ns, bin);
+  }
+}
+
+}  // namespace
+}  // namespace nb

@@ -394,19 +394,6 @@ KernelFn pick_nt(int ntr, bool bin, bool full) {
   }
 }
 
-int resident_per_cu(const void* fn, int threads, size_t lds) {
-  static std::mutex mu;
-  static std::map<std::pair<const void*, size_t>, int> cache;
-  std::lock_guard<std::mutex> lk(mu);
-  auto key = std::make_pair(fn, lds);
-  auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
-  int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, lds) != hipSuccess || per < 1) per = 1;
-  cache[key] = per;
-  return per;
-}
-
 int max_lds_per_block() {
   static int v = 0;
   if (v == 0) {

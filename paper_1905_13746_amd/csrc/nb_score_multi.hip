@@ -215,18 +215,6 @@ KernelFn pick_ns(int ns, bool bin) {
   return nullptr;
 }
 
-int resident_per_cu(const void* fn) {
-  static std::mutex mu;
-  static std::map<const void*, int> cache;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(fn);
-  if (it != cache.end()) return it->second;
-  int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, 0) != hipSuccess || per < 1) per = 1;
-  cache[fn] = per;
-  return per;
-}
-
 }  // namespace
 
 // Entry from nb_score for C >= 3 on the vector ALUs.  Arguments are validated
@@ -265,7 +253,7 @@ int launch_scoreC_valu(const nb_model* m, const nb_layout& L, const void* x, int
   a.wt = wtype;
   a.ns = ns;
   const int64_t ntile = (n + kThreads - 1) / kThreads;
-  const int64_t cap = (int64_t)resident_per_cu(reinterpret_cast<const void*>(fn)) * device_cu_count();
+  const int64_t cap = (int64_t)resident_per_cu(reinterpret_cast<const void*>(fn), kThreads, 0) * device_cu_count();
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(ntile, cap));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), 0, s, a);
   NB_HIP_CHECK(hipGetLastError());

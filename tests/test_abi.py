@@ -131,3 +131,69 @@ def test_route_groups_paper_fixture():
     r = nbg.route_groups(cc, g["min_files"])
     for grp_s, tgt in g["fallback_1based"].items():
         assert r[int(grp_s) - 1] + 1 == tgt
+
+
+def _groups_call(lib, models, groups, xtype=0, wtype=0, tile=0):
+    cm = (_lib.NbModel * len(models))(*models)
+    cg = (_lib.NbGroup * len(groups))(*groups)
+    return lib.nb_score_groups(cm, len(models), cg, len(groups), xtype, wtype, tile, FAKE_DEV, 1 << 20, None)
+
+
+def _group(model, n=10, F=100, **kw):
+    g = _lib.NbGroup(model, 0, FAKE_DEV, n, F, FAKE_DEV, FAKE_DEV, None)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+@pytest.mark.parametrize("case,code", [
+    ("no_model_anywhere", -4), ("index_out_of_range", -1), ("index_below_minus_one", -1),
+    ("three_classes", -1), ("features_differ", -1), ("kinds_differ", -1), ("reserved_set", -1),
+    ("bad_xtype", -1), ("bad_wtype", -1), ("negative_n", -1), ("no_outputs", -1), ("ld_too_small", -1),
+    ("misaligned_log_post", -1),
+])
+def test_score_groups_argument_errors(lib, case, code):
+    """Every argument error is found on the host before any device work."""
+    m2 = [_model(), _model()]
+    groups, models, xt, wt = [_group(0), _group(1)], m2, 0, 0
+    if case == "no_model_anywhere":
+        groups = [_group(-1), _group(-1)]
+    elif case == "index_out_of_range":
+        groups = [_group(0), _group(2)]
+    elif case == "index_below_minus_one":
+        groups = [_group(-2)]
+    elif case == "three_classes":
+        models = [_model(C=3), _model()]
+    elif case == "features_differ":
+        models = [_model(), _model(F=200)]
+    elif case == "kinds_differ":
+        models = [_model(), _model(kind=1)]
+    elif case == "reserved_set":
+        groups = [_group(0, reserved=1)]
+    elif case == "bad_xtype":
+        xt = 5
+    elif case == "bad_wtype":
+        wt = 4
+    elif case == "negative_n":
+        groups = [_group(0, n=-1)]
+    elif case == "no_outputs":
+        groups = [_group(0, labels=None, log_post=None)]
+    elif case == "ld_too_small":
+        groups = [_group(0, ld=99)]
+    elif case == "misaligned_log_post":
+        groups = [_group(0, log_post=FAKE_DEV + 4)]
+    assert _groups_call(lib, models, groups, xt, wt) == code
+    assert lib.nb_last_error()
+
+
+def test_group_plan_rejects_before_allocating(lib):
+    cm = (_lib.NbModel * 1)(_model())
+    cg = (_lib.NbGroup * 1)(_group(-1))
+    out = ctypes.c_void_p(1)
+    assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, 0, 0, None, ctypes.byref(out)) == -4
+    assert not out.value
+    cg = (_lib.NbGroup * 1)(_group(0))
+    assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, -5, 0, None, ctypes.byref(out)) == -1
+    assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, 0, 4, None, ctypes.byref(out)) == -1
+    assert lib.nb_group_plan_destroy(None) == 0
+    assert lib.nb_group_plan_launch(None, None) == -1

@@ -1,0 +1,235 @@
+"""GPU parity of batched size-group scoring (one persistent launch over the
+work items of many groups, each with its own two-class model; groups
+without a model borrow the next group's).  Checked against each group scored
+alone through nb_score (bit-identical: same per-file summation order), the
+FP64 oracle, graph replays against the eager call, and tile invariance."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1905_13746_amd as nbg
+from oracle import groups as og, nb
+from synth import workloads as W
+from tests.parity import X_FP8, X_I32, X_U8, assert_scores, to_np
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+# group sizes: empty, single file, ragged around the 8-file block, larger
+SIZES = [0, 1, 7, 8, 9, 300, 1001, 2500, 64, 33]
+HAS_MODEL = [True, True, False, True, True, False, True, True, True, False]
+
+
+def _build(F, kind, sizes=SIZES, has=HAS_MODEL, xdtype=torch.uint8, fp8=False, train_files=1200):
+    """Train one model per group that has one; make each group's test files."""
+    models, oms, gmodel, xs, xs_oracle = [], [], [], [], []
+    for g, (n, h) in enumerate(zip(sizes, has)):
+        wl = W.group_workload(g, F) if xdtype == torch.uint8 else W.Workload(
+            wid=4, n_classes=2, n_features=F, p_zero=0.7, clip255=False, group=g)
+        if h:
+            X, y = wl.train_set(train_files, device=DEV)
+            m = nbg.Model(2, F, kind)
+            nbg.train(m, X, y)
+            oms.append(nb.train(to_np(X), to_np(y), 2, kind))
+            gmodel.append(len(models))
+            models.append(m)
+        else:
+            gmodel.append(None)
+        Xt, _ = wl.test_set(n, device=DEV)
+        if fp8:
+            q = W.to_fp8_e4m3(Xt)
+            xs.append(q)
+            from oracle import precision as P
+            xs_oracle.append(P.e4m3_value(to_np(q)))
+        else:
+            xs.append(Xt)
+            xs_oracle.append(to_np(Xt))
+    route = og.route(np.array(has))
+    return models, oms, gmodel, xs, xs_oracle, route
+
+
+def _alone(models, gmodel, route, xs, g, wtype, fp8, scores=True):
+    m = models[gmodel[route[g]]]
+    return nbg.score(m, xs[g], wtype=wtype, fp8=fp8, scores=scores)
+
+
+def _assert_equal(got, want):
+    for u, v in zip(got, want):
+        if v is None:
+            assert u is None
+        else:
+            assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+@pytest.mark.parametrize("wtype", [nbg.W_F32, nbg.W_BF16])
+def test_groups_match_alone_and_oracle(kind, wtype):
+    _case(f"groups F=2000 {kind} wtype={wtype}")
+    F = 2000
+    models, oms, gmodel, xs, xo, route = _build(F, kind)
+    outs = nbg.score_groups(models, list(zip(gmodel, xs)), wtype=wtype, scores=True)
+    torch.cuda.synchronize()
+    for g in range(len(SIZES)):
+        if SIZES[g] == 0:
+            continue
+        _assert_equal(outs[g], _alone(models, gmodel, route, xs, g, wtype, False))
+        om = oms[gmodel[route[g]]]
+        lab, lp, sc = outs[g]
+        assert_scores(om, xo[g], to_np(lab), to_np(lp), to_np(sc), wtype=wtype)
+
+
+def test_fallback_routing_is_the_group_rule():
+    # the library's routing equals the oracle's next-then-previous rule
+    r = og.route(np.array(HAS_MODEL))
+    assert list(r) == [0, 1, 3, 3, 4, 6, 6, 7, 8, 8]
+
+
+@pytest.mark.parametrize("F,xdtype,fp8", [(100, torch.uint8, False), (1000, torch.uint8, False),
+                                          (64, torch.int32, False), (500, torch.uint8, True),
+                                          (5000, torch.uint8, False)],
+                         ids=["F100_u8", "F1000_u8", "F64_i32", "F500_fp8", "F5000_u8"])
+def test_groups_other_shapes(F, xdtype, fp8):
+    _case(f"groups F={F} {xdtype} fp8={fp8}")
+    models, oms, gmodel, xs, xo, route = _build(F, nb.MULTINOMIAL, xdtype=xdtype, fp8=fp8)
+    for scores in (False, True):
+        outs = nbg.score_groups(models, list(zip(gmodel, xs)), fp8=fp8, scores=scores)
+        torch.cuda.synchronize()
+        for g in range(len(SIZES)):
+            if SIZES[g] == 0:
+                continue
+            _assert_equal(outs[g], _alone(models, gmodel, route, xs, g, nbg.W_F32, fp8, scores))
+            lab, lp, sc = outs[g]
+            xt = X_FP8 if fp8 else (X_I32 if xdtype == torch.int32 else X_U8)
+            assert_scores(oms[gmodel[route[g]]], xo[g], to_np(lab), to_np(lp),
+                          None if sc is None else to_np(sc), xtype=xt)
+
+
+def test_tile_invariance():
+    _case("groups tile invariance")
+    models, _, gmodel, xs, _, _ = _build(2000, nb.MULTINOMIAL)
+    ref = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True)
+    for tile in (1, 8, 40, 1000, 1 << 20):
+        got = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True, tile_rows=tile)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, got):
+            _assert_equal(b, a)
+
+
+def test_plan_graph_replays_equal_eager():
+    _case("groups plan replay")
+    models, _, gmodel, xs, _, _ = _build(2000, nb.MULTINOMIAL)
+    eager = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True)
+    plan = nbg.GroupPlan(models, list(zip(gmodel, xs)), scores=True)
+    info = plan.info()
+    assert info["n_files"] == sum(SIZES) and info["n_items"] > 0 and info["grid"] >= 1
+    for rep in range(4):
+        for o in plan.outs:
+            for t in o:
+                if t is not None:
+                    t.fill_(-7)
+        # unrelated eager work on the same stream between replays
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for g in range(len(SIZES)):
+            _assert_equal(plan.outs[g], eager[g])
+    plan.close()
+
+
+def test_plan_new_data_in_same_buffers():
+    _case("groups plan refill")
+    models, oms, gmodel, xs, _, route = _build(1000, nb.MULTINOMIAL)
+    plan = nbg.GroupPlan(models, list(zip(gmodel, xs)))
+    for step in range(2):
+        for g, x in enumerate(xs):
+            if x.shape[0]:
+                wl = W.group_workload(g, 1000)
+                x.copy_(wl.test_set(x.shape[0], device=DEV, row0=1000 * (step + 1))[0])
+        plan.launch()
+        torch.cuda.synchronize()
+        for g in range(len(SIZES)):
+            if SIZES[g]:
+                _assert_equal(plan.outs[g], _alone(models, gmodel, route, xs, g, nbg.W_F32, False, False))
+    plan.close()
+
+
+def test_plan_autotune_and_cache(tmp_path):
+    _case("groups plan tune")
+    path = str(tmp_path / "tiles.json")
+    os.environ["NB_TUNE_CACHE"] = path
+    try:
+        models, _, gmodel, xs, _, route = _build(2000, nb.MULTINOMIAL)
+        groups = list(zip(gmodel, xs))
+        p1 = nbg.GroupPlan(models, groups, tune=True)
+        i1 = p1.info()
+        assert i1["tuned"] == 1 and i1["tile_rows"] % i1["rows_per_block"] == 0
+        p1.launch()
+        torch.cuda.synchronize()
+        for g in range(len(SIZES)):
+            if SIZES[g]:
+                _assert_equal(p1.outs[g], _alone(models, gmodel, route, xs, g, nbg.W_F32, False, False))
+        p2 = nbg.GroupPlan(models, groups, tune=True)
+        assert p2.info()["tuned"] == 2 and p2.info()["tile_rows"] == i1["tile_rows"]
+        with open(path) as f:
+            text = f.read()
+        assert "score2_groups/F2000" in text
+        p1.close()
+        p2.close()
+    finally:
+        del os.environ["NB_TUNE_CACHE"]
+
+
+def test_groups_argument_errors():
+    models, _, gmodel, xs, _, _ = _build(100, nb.MULTINOMIAL, sizes=[5, 6], has=[True, True], train_files=200)
+    with pytest.raises(nbg.NBError) as e:
+        nbg.score_groups(models, [(None, xs[0]), (None, xs[1])])
+    assert e.value.code == -4                                  # no model anywhere
+    other = nbg.Model(2, 200)
+    with pytest.raises(nbg.NBError):
+        nbg.score_groups([models[0], other], [(0, xs[0]), (1, xs[1])])   # F differs
+    three = nbg.Model(3, 100)
+    with pytest.raises(nbg.NBError):
+        nbg.score_groups([three], [(0, xs[0])])                # not two classes
+    with pytest.raises(nbg.NBError):
+        nbg.score_groups(models, [(2, xs[0])])                 # index out of range
+
+
+@pytest.mark.slow
+def test_groups_full_size_sampled():
+    """The 256-group lognormal workload (F = 2000) in the benchmark's plan
+    configuration: whole groups against nb_score alone, sampled files of
+    every group against the oracle."""
+    sizes = W.group_sizes()
+    F = 2000
+    rng = np.random.default_rng(11)
+    models, oms, xs = [], [], []
+    for g, n in enumerate(sizes):
+        _case(f"full-size group {g} n={n}") if g % 64 == 0 else None
+        wl = W.group_workload(g, F)
+        X, y = wl.train_set(min(2 * int(n), 4000), device=DEV)
+        m = nbg.Model(2, F, nb.MULTINOMIAL)
+        nbg.train(m, X, y)
+        models.append(m)
+        oms.append((wl, X, y))
+        xs.append(wl.test_set(int(n), device=DEV)[0])
+    plan = nbg.GroupPlan(models, [(g, x) for g, x in enumerate(xs)], scores=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    for g in range(len(sizes)):
+        if g % 16 == 0:
+            _assert_equal(plan.outs[g], nbg.score(models[g], xs[g], scores=True))
+        wl, X, y = oms[g]
+        om = nb.train(to_np(X), to_np(y), 2, nb.MULTINOMIAL)
+        idx = rng.choice(int(sizes[g]), size=min(24, int(sizes[g])), replace=False)
+        lab, lp, sc = plan.outs[g]
+        ii = torch.from_numpy(idx).to(DEV)
+        assert_scores(om, to_np(xs[g][ii]), to_np(lab[ii]), to_np(lp[ii]), to_np(sc[ii]))
+    plan.close()

@@ -59,6 +59,8 @@ def parse():
                     help="repeat the oracle's step until this much CPU time has been spent")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--leg", choices=["f_sweep", "precision", "groups", "serve"],
+                    help="run only this extra leg and print its JSON (used for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--fill-inputs", action="store_true",
                     help="constant-filled inputs instead of the seeded generator (for hardware-counter runs: "
@@ -107,6 +109,23 @@ def load_traffic(path):
         return None
 
 
+def oracle_all_cores(wl, Xtr, ytr, Xte, seconds: float):
+    """The same oracle step with every host core available to its BLAS."""
+    from oracle import nb
+    xtr, ytr_, xte = Xtr.cpu().numpy(), ytr.cpu().numpy(), Xte.cpu().numpy()
+    reps, sec = 0, 0.0
+    while sec < seconds and reps < 50:
+        t0 = time.perf_counter()
+        om = nb.train(xtr, ytr_, wl.n_classes, nb.MULTINOMIAL)
+        nb.classify(om, xte)
+        sec += time.perf_counter() - t0
+        reps += 1
+    from threadpoolctl import threadpool_info
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {"value": reps * xte.shape[0] / sec, "unit": "files/s", "cores": threads, "kind": "oracle",
+            "sample": f"the full step x {reps} repetitions, numpy FP64, BLAS with {threads} threads, {sec:.1f} s"}
+
+
 def cpu_baseline(wl, Xtr, ytr, Xte, seconds: float):
     """The oracle as it stands, single-threaded (the paper's sequential
     program), on the same step: train on the 200,000 files, score the
@@ -148,12 +167,29 @@ def f_sweep(nbg, W):
     return out
 
 
-def precision_compare(nbg, W):
+def precision_compare(nbg, W, fill: bool = False):
     """16 classes, F = 4096, 4M files: FP32 table on the vector ALUs vs the
-    BF16 table on the matrix cores, uint8 and FP8-e4m3 features."""
+    BF16 table on the matrix cores, uint8 and FP8-e4m3 features.  fill:
+    constant-filled inputs and no oracle comparison (for counter runs, whose
+    collector cannot run the seeded generator's kernels)."""
     from oracle import nb
     wl = W.family16()
     F, C = wl.n_features, wl.n_classes
+    if fill:
+        X = torch.full((W.FAMILY_TRAIN // 8, F), 1, dtype=torch.uint8, device="cuda")
+        y = (torch.arange(X.shape[0], device="cuda") % C).to(torch.int32)
+        m = nbg.Model(C, F, "multinomial")
+        nbg.train(m, X, y)
+        del X, y
+        Xt = torch.full((W.FAMILY_TEST, F), 2, dtype=torch.uint8, device="cuda")
+        n = Xt.shape[0]
+        lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        lp = torch.empty((n, C), dtype=torch.float32, device="cuda")
+        res = {"workload": f"{C} classes, F={F}, {n} constant-filled files (counter run)"}
+        for name, kw in (("fp32_vector", {"wtype": 0}), ("bf16_mfma_u8", {"wtype": 1})):
+            ms = timed(lambda: nbg.score(m, Xt, out=(lab, lp, None), **kw), 3)
+            res[name] = {"ms": ms, "GBps": n * (F + 4 + 4 * C) / (ms / 1e3) / 1e9}
+        return res
     X, y = wl.train_set(W.FAMILY_TRAIN, device="cuda")
     m = nbg.Model(C, F, "multinomial")
     nbg.train(m, X, y)
@@ -312,6 +348,13 @@ def main():
         return
     import paper_1905_13746_amd as nbg
     from synth import workloads as W
+    if args.leg:
+        if args.leg == "precision":
+            res = precision_compare(nbg, W, fill=args.fill_inputs)
+        else:
+            res = {"f_sweep": f_sweep, "groups": groups_leg, "serve": serve_leg}[args.leg](nbg, W)
+        print(json.dumps({"leg": args.leg, **res}), flush=True)
+        return
 
     F = args.features
     wl = W.binary_u8(F)
@@ -357,7 +400,8 @@ def main():
     if nbg.model_status(model) != 0:
         raise RuntimeError("training failed in the timed steps")
 
-    score_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    score_ms = float(launch_ms.mean())
     algo_bytes = n * (F + 4 + 2 * 4)
     achieved = algo_bytes / (score_ms / 1e3) / 1e9
     try:
@@ -385,11 +429,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": load_traffic(args.traffic),
                      "kernel": "score2_kernel (two classes, uint8, 64 lanes per file)",
-                     "avg_launch_ms": score_ms, "algorithmic_bytes_per_launch": algo_bytes,
+                     "avg_launch_ms": score_ms,
+                     "launch_ms_p10_p50_p90": [float(np.percentile(launch_ms, q)) for q in (10, 50, 90)],
+                     "algorithmic_bytes_per_launch": algo_bytes,
                      "scoring_files_per_s": n / (score_ms / 1e3), "probe_read_GBps": probe},
     }
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl, Xtr, ytr, Xte, args.cpu_seconds)
+        if not args.no_extras:
+            rec["oracle_all_cores"] = oracle_all_cores(wl, Xtr, ytr, Xte, args.cpu_seconds)
     if not args.no_extras:
         del Xtr, ytr, Xte
         torch.cuda.empty_cache()

@@ -170,9 +170,13 @@ int nb_route_groups(const int64_t* class_counts_host, int32_t n_groups, int32_t 
  * a model is classified with the model of the next group that has one (the
  * first such group after it in `groups`, else the nearest one before it:
  * the rule of nb_route_groups).  Every group of a call is scored by ONE
- * persistent kernel launch over (group, tile) work items; each file's
- * results are bit-identical to nb_score of its group alone (same summation
- * order), whatever the tile, the grid or the other groups.
+ * persistent kernel launch over the concatenation of the groups' files;
+ * each file's results are bit-identical to nb_score of its group alone
+ * (same summation order), whatever the schedule, tile or grid.
+ * Schedules: static ranges (each workgroup scores an equal contiguous run
+ * of files, staging a group's table in LDS when its run enters that group)
+ * or dynamic items (groups cut into tiles of tile_rows files, taken largest
+ * first from a device counter).
  *
  * One group of files (device pointers as for nb_score): */
 typedef struct {
@@ -189,8 +193,8 @@ typedef struct {
 /* Requirements: every model a group uses has two classes, and all of them
  * share the kind and the feature count F (the paper keeps k features per
  * group).  Each non-empty group needs at least one output.
- * tile_rows: files per work item (rounded up to whole blocks of the kernel);
- * 0 picks about four items per resident workgroup.
+ * tile_rows: 0 = static ranges; > 0 = dynamic items of that many files
+ * (rounded up to whole blocks of the kernel).
  * Errors: NB_EINVAL (arguments, per group), NB_ENOMODEL (every model is -1),
  * NB_ENOMEM (workspace too small), NB_EHIP. */
 
@@ -211,23 +215,27 @@ int nb_score_groups(const nb_model* models, int32_t n_models, const nb_group* gr
  * input buffers is scored with no host work.  Creation allocates device
  * memory (hipMalloc) and synchronises `stream`; launching allocates nothing.
  * Launches of one plan must not overlap (they share the work counter).
- * Tile choice (tile_rows == 0): a tile recorded for the same shape (kept in
- * memory, and in the JSON file named by the NB_TUNE_CACHE environment
- * variable when set), else with NB_PLAN_TUNE the fastest of several tiles
- * timed on the caller's data (this scores the groups, writing the outputs,
- * a few times), else the default above. */
+ * Schedule choice (tile_rows == 0): one recorded for the same shape (kept
+ * in memory, and in the JSON file named by the NB_TUNE_CACHE environment
+ * variable when set), else with NB_PLAN_TUNE the fastest of static ranges
+ * and several dynamic tiles, timed on the caller's data (this scores the
+ * groups, writing the outputs, a few times), else static ranges.
+ * tile_rows > 0 fixes dynamic items of that size. */
 typedef struct nb_group_plan nb_group_plan;
 #define NB_PLAN_TUNE 1
 
+#define NB_SCHEDULE_STATIC  0
+#define NB_SCHEDULE_DYNAMIC 1
+
 typedef struct {
-  int32_t tile_rows;       /* files per full work item                         */
-  int32_t n_items;         /* work items of one launch                         */
+  int32_t tile_rows;       /* files per workgroup run (static) or full item    */
+  int32_t n_items;         /* runs (static) or items (dynamic) of one launch   */
   int32_t grid;            /* workgroups launched                              */
   int32_t tuned;           /* 0 default or caller's tile, 1 timed, 2 cached    */
   int64_t n_files;         /* files scored per launch                          */
   int32_t rows_per_block;  /* files per wave block of the kernel               */
   int32_t lds_bytes;       /* table bytes staged in LDS per workgroup          */
-  int32_t reserved;
+  int32_t schedule;        /* NB_SCHEDULE_STATIC or NB_SCHEDULE_DYNAMIC        */
 } nb_group_plan_info;
 
 int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,

@@ -267,7 +267,9 @@ class GroupPlan:
     def info(self) -> dict:
         inf = _lib.NbGroupPlanInfo()
         check(self._lib.nb_group_plan_query(self.handle, ctypes.byref(inf)), "nb_group_plan_query")
-        return {k: getattr(inf, k) for k, _ in inf._fields_ if k != "reserved"}
+        d = {k: getattr(inf, k) for k, _ in inf._fields_}
+        d["schedule"] = "static" if d["schedule"] == 0 else "dynamic"
+        return d
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -38,9 +38,12 @@ __device__ __forceinline__ u32x4 load16_guarded(const uint8_t* p, int64_t avail)
 // `bytes` return zero instead of touching memory.  Word 3 is the gfx9-family
 // descriptor format for untyped dword access.
 // `bytes` is clamped to [0, 2^31 - 1] (the descriptor field).
+// The clamp uses 32-bit halves only: gfx9 has no 64-bit scalar ordered
+// compare, and a 64-bit vector compare would need VGPRs (possibly ones with
+// loads still in flight).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
-  const uint64_t b = (uint64_t)(bytes < 0 ? 0 : bytes);
-  const int32_t n = (b >> 31) ? 0x7FFFFFFF : (int32_t)b;
+  const uint32_t hi = (uint32_t)((uint64_t)bytes >> 32), lo = (uint32_t)bytes;
+  const int32_t n = ((int32_t)hi < 0) ? 0 : ((hi != 0u || (lo >> 31) != 0u) ? 0x7FFFFFFF : (int32_t)lo);
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
 }
 

@@ -2,24 +2,28 @@
 // size groups and each group is classified by its own two-class model; a
 // group without a model borrows the next trained group's).
 //
-// All groups of a call are scored by ONE persistent launch.  The host cuts
-// every group into work items of at most `tile` blocks (a block is the
-// two-class kernel's unit: R row-steps of 64/LPR files) and sorts the items
-// largest first.  Each workgroup repeatedly takes the next item from a
-// device counter, stages that group's scoring rows in LDS and streams the
-// item's blocks with the same per-wave pipeline as the single-model kernel
-// (its four waves take every fourth block).  Taking items in decreasing
-// size is the longest-processing-time rule: the imbalance at the end of the
-// launch is at most one small item per workgroup.
-//
-// The counter pair (next item, finished workgroups) is zero between
-// launches: the last workgroup to finish re-arms it, so a captured graph
-// replays the launch with no memset node.  Launches that share a counter
-// (one plan, or one workspace) must not overlap.
+// All groups of a call are scored by ONE persistent launch over the
+// concatenation of every group's blocks (a block is the two-class kernel's
+// unit: R row-steps of 64/LPR files).  Two schedules:
+//   * static ranges (the default): workgroup w takes the w-th of grid equal
+//     contiguous runs of blocks.  A run crosses few group boundaries (a group
+//     averages hundreds of blocks); at each one the workgroup stages the new
+//     group's scoring rows in LDS and goes on.  The four waves of a
+//     workgroup take every fourth block of the run, with the single-model
+//     kernel's pipeline.  Balanced by construction, no atomics.
+//   * dynamic items: the host cuts every group into items of at most `tile`
+//     blocks, sorted largest first; each workgroup takes the next item from
+//     a device counter (longest-processing-time order: at most one small
+//     item of imbalance per workgroup at the end).  The counter pair (next
+//     item, finished workgroups) is zero between launches: the last
+//     workgroup to finish re-arms it, so a captured graph replays the launch
+//     with no memset node.  Launches that share a counter must not overlap.
+// A plan times both (and several tiles) and keeps the fastest.
 //
 // Each file's summation order is that of the single-model kernel for the
 // same (F, xtype): results are identical to scoring each group alone with
-// nb_score, whatever the tile, the grid or the order in which items run.
+// nb_score, whatever the schedule, the tile, the grid or the order in which
+// work runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,10 +52,42 @@ static_assert(sizeof(Score2Args) <= kGroupDescBound, "descriptor bound used by s
 
 struct GroupsArgs {
   const Score2Args* descs;   // [n_groups]
-  const GroupItem* items;    // [n_items], largest first
-  int32_t* counter;          // [2]: next item, finished workgroups
+  const GroupItem* items;    // dynamic: [n_items], largest first
+  const int64_t* gstart;     // static: [n_groups + 1] first block of each group
+  int32_t* counter;          // dynamic: [2] next item, finished workgroups
   int32_t n_items;
+  int32_t n_groups;
+  int64_t total_blocks;
 };
+
+template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+__global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsArgs g) {
+  extern __shared__ float tbl[];        // [NS][Fp] of the current group
+  __shared__ float stage[kWaves][NS][(64 / LPR) * kRowSteps];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t B = g.total_blocks;
+  int64_t b = B * blockIdx.x / gridDim.x;
+  const int64_t b1 = B * (blockIdx.x + 1) / gridDim.x;
+  if (b >= b1) return;
+  // the group holding block b: the last gi with gstart[gi] <= b
+  int lo = 0, hi = g.n_groups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.gstart[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  for (int gi = lo; b < b1; ++gi) {
+    const int64_t gs = g.gstart[gi];
+    const int64_t seg_end = min(b1, g.gstart[gi + 1]);
+    if (seg_end <= b) continue;                 // empty group
+    const Score2Args a = g.descs[gi];
+    __syncthreads();                            // the previous group's table is no longer read
+    stage_table<NS>(a, tbl);
+    __syncthreads();
+    score_blocks<XT, LPR, NS, BIN, MULTI>(a, tbl, (b - gs) + wave, kWaves, seg_end - gs, stage);
+    b = seg_end;
+  }
+}
 
 template <int XT, int LPR, int NS, bool BIN, bool MULTI>
 __global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g) {
@@ -90,6 +126,13 @@ struct Grouped {
   }
 };
 
+struct GroupedStatic {
+  template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+  static const void* fn() {
+    return reinterpret_cast<const void*>(score2_groups_static_kernel<XT, LPR, NS, BIN, MULTI>);
+  }
+};
+
 constexpr size_t kCounterBytes = 256;
 
 // Everything the host knows about one grouped call, before any device work.
@@ -101,8 +144,10 @@ struct GroupSetup {
   bool bin = false;
   int xtype = 0, wtype = 0;
   size_t lds = 0;
-  const void* fn = nullptr;
+  const void* fn = nullptr;        // dynamic-item kernel
+  const void* fn_static = nullptr; // static-range kernel
   int grid_cap = 1;                // resident workgroups on the device
+  int64_t total_blocks = 0;
 };
 
 int setup_groups(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups, int32_t xtype,
@@ -166,9 +211,13 @@ int setup_groups(const nb_model* models, int32_t n_models, const nb_group* group
   const int cw = 16 * S->lpr;
   S->nch = (S->F + cw - 1) / cw;
   S->fn = pick_score2<Grouped>(xtype, S->lpr, S->nch > 1, S->ns, S->bin);
-  if (S->lds > 64 * 1024)
+  S->fn_static = pick_score2<GroupedStatic>(xtype, S->lpr, S->nch > 1, S->ns, S->bin);
+  if (S->lds > 64 * 1024) {
     NB_HIP_CHECK(hipFuncSetAttribute(S->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds));
+    NB_HIP_CHECK(hipFuncSetAttribute(S->fn_static, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds));
+  }
   S->grid_cap = resident_per_cu(S->fn, kThreads, S->lds) * device_cu_count();
+  for (int64_t b : S->blocks) S->total_blocks += b;
   return NB_OK;
 }
 
@@ -199,14 +248,48 @@ std::vector<GroupItem> make_items(const GroupSetup& S, int tile_blocks) {
   return items;
 }
 
-size_t workspace_bytes(size_t n_groups, size_t n_items) {
-  return kCounterBytes + align_up(n_groups * sizeof(Score2Args), kAlign) + align_up(n_items * sizeof(GroupItem), kAlign);
+// A schedule is a tile size in blocks: 0 = static ranges, > 0 = dynamic
+// items of at most that many blocks.  Its device image (the work list):
+//   [256-byte header: two zeroed int32 counters]
+//   [descriptors, one per group]
+//   [payload: items (dynamic) or the first block of each group plus the
+//    total (static: n_groups + 1 int64)]
+struct WorkList {
+  int tile_blocks = 0;
+  std::vector<GroupItem> items;
+  std::vector<int64_t> gstart;
+  int32_t n_items() const { return (int32_t)items.size(); }
+};
+
+WorkList make_work_list(const GroupSetup& S, int tile_blocks) {
+  WorkList w;
+  w.tile_blocks = tile_blocks;
+  if (tile_blocks == 0) {
+    w.gstart.resize(S.blocks.size() + 1);
+    int64_t acc = 0;
+    for (size_t g = 0; g < S.blocks.size(); ++g) {
+      w.gstart[g] = acc;
+      acc += S.blocks[g];
+    }
+    w.gstart[S.blocks.size()] = acc;
+  } else {
+    w.items = make_items(S, tile_blocks);
+  }
+  return w;
+}
+
+size_t payload_bytes(const WorkList& w) {
+  return w.tile_blocks == 0 ? w.gstart.size() * sizeof(int64_t) : w.items.size() * sizeof(GroupItem);
+}
+
+size_t work_list_bytes(size_t n_groups, size_t payload) {
+  return kCounterBytes + align_up(n_groups * sizeof(Score2Args), kAlign) + align_up(payload, kAlign);
 }
 
 struct DevLists {
   int32_t* counter;
   Score2Args* descs;
-  GroupItem* items;
+  void* payload;
 };
 
 DevLists carve(void* ws, size_t n_groups) {
@@ -214,39 +297,67 @@ DevLists carve(void* ws, size_t n_groups) {
   DevLists d;
   d.counter = reinterpret_cast<int32_t*>(p);
   d.descs = reinterpret_cast<Score2Args*>(p + kCounterBytes);
-  d.items = reinterpret_cast<GroupItem*>(p + kCounterBytes + align_up(n_groups * sizeof(Score2Args), kAlign));
+  d.payload = p + kCounterBytes + align_up(n_groups * sizeof(Score2Args), kAlign);
   return d;
 }
 
-int launch_grouped(const void* fn, size_t lds, int grid, const DevLists& d, int32_t n_items, hipStream_t s) {
-  if (n_items == 0) return NB_OK;
+// The device image of a work list (counters zeroed).
+void serialise(const GroupSetup& S, const WorkList& w, std::vector<uint8_t>* blob) {
+  const size_t ng = S.descs.size();
+  blob->assign(work_list_bytes(ng, payload_bytes(w)), 0);
+  std::memcpy(blob->data() + kCounterBytes, S.descs.data(), ng * sizeof(Score2Args));
+  uint8_t* pay = blob->data() + kCounterBytes + align_up(ng * sizeof(Score2Args), kAlign);
+  if (w.tile_blocks == 0) std::memcpy(pay, w.gstart.data(), payload_bytes(w));
+  else std::memcpy(pay, w.items.data(), payload_bytes(w));
+}
+
+// Launch geometry of a schedule: the kernel and the number of workgroups.
+struct Geometry {
+  const void* fn = nullptr;
+  int grid = 0;
+};
+
+Geometry geometry(const GroupSetup& S, const WorkList& w) {
+  Geometry G;
+  if (w.tile_blocks == 0) {
+    G.fn = S.fn_static;
+    // every workgroup gets at least a few blocks per wave
+    const int64_t most = std::max<int64_t>(1, S.total_blocks / (2 * kWaves));
+    G.grid = (int)std::max<int64_t>(1, std::min<int64_t>(S.grid_cap, most));
+  } else {
+    G.fn = S.fn;
+    G.grid = std::max(1, std::min(S.grid_cap, w.n_items()));
+  }
+  return G;
+}
+
+int launch_grouped(const void* fn, size_t lds, int grid, const DevLists& d, int32_t n_groups, int32_t n_items,
+                   int64_t total_blocks, bool is_static, hipStream_t s) {
+  if (total_blocks == 0) return NB_OK;
   GroupsArgs g;
   g.descs = d.descs;
-  g.items = d.items;
+  g.items = is_static ? nullptr : static_cast<const GroupItem*>(d.payload);
+  g.gstart = is_static ? static_cast<const int64_t*>(d.payload) : nullptr;
   g.counter = d.counter;
   g.n_items = n_items;
+  g.n_groups = n_groups;
+  g.total_blocks = total_blocks;
   void* args[] = {&g};
   NB_HIP_CHECK(hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s));
   NB_HIP_CHECK(hipGetLastError());
   return NB_OK;
 }
 
-int launch_grouped(const GroupSetup& S, const DevLists& d, int32_t n_items, hipStream_t s) {
-  return launch_grouped(S.fn, S.lds, std::max(1, std::min(S.grid_cap, n_items)), d, n_items, s);
-}
-
-// The device image of a work list: zeroed counters, descriptors, items.
-void serialise(const GroupSetup& S, const std::vector<GroupItem>& items, std::vector<uint8_t>* blob) {
-  const size_t ng = S.descs.size();
-  blob->assign(workspace_bytes(ng, items.size()), 0);
-  std::memcpy(blob->data() + kCounterBytes, S.descs.data(), ng * sizeof(Score2Args));
-  std::memcpy(blob->data() + kCounterBytes + align_up(ng * sizeof(Score2Args), kAlign), items.data(),
-              items.size() * sizeof(GroupItem));
+int launch_grouped(const GroupSetup& S, const WorkList& w, const DevLists& d, hipStream_t s) {
+  const Geometry G = geometry(S, w);
+  return launch_grouped(G.fn, S.lds, G.grid, d, (int32_t)S.descs.size(), w.n_items(), S.total_blocks,
+                        w.tile_blocks == 0, s);
 }
 
 // ------------------------------------------------------------ tile cache
-// Tuned tiles persist in a flat JSON object {"key": tile_blocks, ...} at the
-// path named by NB_TUNE_CACHE (when set); always kept in memory.
+// Tuned schedules persist in a flat JSON object {"key": tile_blocks, ...}
+// (0 = static ranges) at the path named by NB_TUNE_CACHE (when set); always
+// kept in memory.
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
@@ -276,7 +387,7 @@ void tune_load_locked() {
     size_t k = t.find(':', j);
     if (k == std::string::npos) break;
     const int v = std::atoi(t.c_str() + k + 1);
-    if (v > 0) g_tune[key] = v;
+    if (v >= 0) g_tune[key] = v;
     i = t.find_first_of(",}", k);
     if (i == std::string::npos) break;
   }
@@ -296,11 +407,12 @@ void tune_store_locked() {
   f << "\n}\n";
 }
 
+// tile in blocks (0 = static ranges), or -1 when the shape was never tuned
 int tune_lookup(const std::string& key) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
   auto it = g_tune.find(key);
-  return it == g_tune.end() ? 0 : it->second;
+  return it == g_tune.end() ? -1 : it->second;
 }
 
 void tune_record(const std::string& key, int tile_blocks) {
@@ -319,20 +431,23 @@ int prepare_group_launch(const nb_model* models, int32_t n_models, const nb_grou
   int rc = setup_groups(models, n_models, groups, n_groups, xtype, wtype, &S);
   if (rc) return rc;
   if (tile_rows < 0) return fail(NB_EINVAL, "tile_rows must be >= 0");
-  const int tb = tile_rows > 0 ? tile_blocks_from_rows(S, tile_rows) : default_tile_blocks(S);
-  const std::vector<GroupItem> items = make_items(S, tb);
-  serialise(S, items, blob);
-  out->fn = S.fn;
+  const WorkList w = make_work_list(S, tile_rows > 0 ? tile_blocks_from_rows(S, tile_rows) : 0);
+  serialise(S, w, blob);
+  const Geometry G = geometry(S, w);
+  out->fn = G.fn;
   out->lds = S.lds;
-  out->n_items = (int32_t)items.size();
+  out->grid = G.grid;
+  out->n_items = w.n_items();
   out->n_groups = n_groups;
-  out->grid = std::max(1, std::min(S.grid_cap, out->n_items));
+  out->is_static = w.tile_blocks == 0;
+  out->total_blocks = S.total_blocks;
   out->blob_bytes = blob->size();
   return NB_OK;
 }
 
 int enqueue_group_launch(const GroupLaunch& L, void* dev_blob, hipStream_t s) {
-  return launch_grouped(L.fn, L.lds, L.grid, carve(dev_blob, L.n_groups), L.n_items, s);
+  return launch_grouped(L.fn, L.lds, L.grid, carve(dev_blob, L.n_groups), L.n_groups, L.n_items, L.total_blocks,
+                        L.is_static, s);
 }
 
 }  // namespace nb
@@ -342,48 +457,49 @@ using namespace nb;
 // ------------------------------------------------------------------ plan
 struct nb_group_plan {
   GroupSetup S;
-  void* dev = nullptr;            // counters, descriptors, items
+  void* dev = nullptr;            // work list: counters, descriptors, payload
+  size_t dev_bytes = 0;
   int32_t n_groups = 0;
-  int32_t n_items = 0;
-  int tile_blocks = 0;
+  WorkList w;
   int tuned = 0;
-  int grid = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-int upload_items(nb_group_plan* p, const std::vector<GroupItem>& items) {
-  const DevLists d = carve(p->dev, p->n_groups);
-  NB_HIP_CHECK(hipMemcpy(d.items, items.data(), items.size() * sizeof(GroupItem), hipMemcpyHostToDevice));
-  p->n_items = (int32_t)items.size();
-  p->grid = std::max(1, std::min(p->S.grid_cap, p->n_items));
+int upload(nb_group_plan* p, const WorkList& w) {
+  std::vector<uint8_t> blob;
+  serialise(p->S, w, &blob);
+  if (blob.size() > p->dev_bytes) return fail(NB_EHIP, "internal: work list larger than its buffer");
+  NB_HIP_CHECK(hipMemcpy(p->dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  p->w = w;
   return NB_OK;
 }
 
-// Time the launch at a few tiles on the caller's data; keep the fastest.
+// Time the static schedule and several dynamic tiles on the caller's data;
+// keep the fastest.
 int autotune(nb_group_plan* p, hipStream_t s) {
-  std::vector<int> cand;
+  std::vector<int> cand = {0};
   const int def = default_tile_blocks(p->S);
-  for (int t : {4, 8, 16, 32, 64, 128, def}) cand.push_back(t);
-  std::sort(cand.begin(), cand.end());
+  for (int t : {8, 16, 32, 64, 128, def}) cand.push_back(t);
+  std::sort(cand.begin() + 1, cand.end());
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   hipEvent_t e0, e1;
   NB_HIP_CHECK(hipEventCreate(&e0));
   NB_HIP_CHECK(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_t = def;
+  int best_t = 0;
   int rc = NB_OK;
+  const DevLists d = carve(p->dev, p->n_groups);
   for (int t : cand) {
-    const auto items = make_items(p->S, t);
-    if ((rc = upload_items(p, items))) break;
-    const DevLists d = carve(p->dev, p->n_groups);
-    if ((rc = launch_grouped(p->S, d, p->n_items, s))) break;   // warm
+    const WorkList w = make_work_list(p->S, t);
+    if ((rc = upload(p, w))) break;
+    if ((rc = launch_grouped(p->S, w, d, s))) break;   // warm
     float tot = 0.0f;
     for (int r = 0; r < 3 && rc == NB_OK; ++r) {
       if (hipEventRecord(e0, s) != hipSuccess) rc = fail(NB_EHIP, "hipEventRecord");
-      if (!rc) rc = launch_grouped(p->S, d, p->n_items, s);
+      if (!rc) rc = launch_grouped(p->S, w, d, s);
       if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(NB_EHIP, "hipEventRecord");
       if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(NB_EHIP, "hipEventSynchronize");
       float ms = 0.0f;
@@ -399,7 +515,7 @@ int autotune(nb_group_plan* p, hipStream_t s) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
-  p->tile_blocks = best_t;
+  p->w.tile_blocks = best_t;
   p->tuned = 1;
   return NB_OK;
 }
@@ -417,29 +533,26 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
   int rc = setup_groups(models, n_models, groups, n_groups, xtype, wtype, &p->S);
   if (rc) return rc;
   p->n_groups = n_groups;
-  // room for the smallest tile's item list: every later list is shorter
-  const size_t max_items = make_items(p->S, kWaves).size();
-  NB_HIP_CHECK(hipMalloc(&p->dev, workspace_bytes(n_groups, max_items)));
-  const DevLists d = carve(p->dev, n_groups);
-  {
-    std::vector<uint8_t> blob;     // zeroed counters and the descriptors
-    serialise(p->S, {}, &blob);
-    NB_HIP_CHECK(hipStreamSynchronize(s));
-    NB_HIP_CHECK(hipMemcpy(p->dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
-  }
+  // room for the largest work list any schedule makes (the smallest tile)
+  const WorkList smallest = make_work_list(p->S, kWaves);
+  p->dev_bytes = std::max(work_list_bytes(n_groups, payload_bytes(smallest)),
+                          work_list_bytes(n_groups, (n_groups + 1) * sizeof(int64_t)));
+  NB_HIP_CHECK(hipStreamSynchronize(s));
+  NB_HIP_CHECK(hipMalloc(&p->dev, p->dev_bytes));
   const std::string key = tune_key(p->S, n_groups);
+  int tile = 0;
   if (tile_rows > 0) {
-    p->tile_blocks = tile_blocks_from_rows(p->S, tile_rows);
-  } else if (int t = tune_lookup(key)) {
-    p->tile_blocks = t;
+    tile = tile_blocks_from_rows(p->S, tile_rows);
+  } else if ((tile = tune_lookup(key)) >= 0) {
     p->tuned = 2;
   } else if (flags & NB_PLAN_TUNE) {
     if ((rc = autotune(p, s))) return rc;
-    tune_record(key, p->tile_blocks);
+    tile = p->w.tile_blocks;
+    tune_record(key, tile);
   } else {
-    p->tile_blocks = default_tile_blocks(p->S);
+    tile = 0;
   }
-  if ((rc = upload_items(p, make_items(p->S, p->tile_blocks)))) return rc;
+  if ((rc = upload(p, make_work_list(p->S, tile)))) return rc;
   // capture the launch into a graph on a private stream
   hipStream_t cs;
   NB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -447,7 +560,7 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
     hipStreamDestroy(cs);
     return fail(NB_EHIP, "hipStreamBeginCapture failed");
   }
-  rc = launch_grouped(p->S, d, p->n_items, cs);
+  rc = launch_grouped(p->S, p->w, carve(p->dev, n_groups), cs);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &graph);
   hipStreamDestroy(cs);
@@ -480,7 +593,7 @@ int nb_score_groups(const nb_model* models, int32_t n_models, const nb_group* gr
   GroupLaunch L;
   int rc = prepare_group_launch(models, n_models, groups, n_groups, xtype, wtype, tile_rows, &blob, &L);
   if (rc) return rc;
-  if (L.n_items == 0) return NB_OK;
+  if (L.total_blocks == 0) return NB_OK;
   if (!workspace) return fail(NB_EINVAL, "workspace is NULL");
   if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
     return fail(NB_EINVAL, "workspace must be 256-byte aligned");
@@ -505,7 +618,7 @@ int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_grou
   const int rc = plan_build(p, models, n_models, groups, n_groups, xtype, wtype, tile_rows, flags,
                             reinterpret_cast<hipStream_t>(stream));
   if (rc) {
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     plan_free(p);
     return rc;
   }
@@ -515,21 +628,25 @@ int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_grou
 
 int nb_group_plan_launch(nb_group_plan* plan, void* stream) {
   if (!plan) return fail(NB_EINVAL, "plan is NULL");
-  if (plan->n_items == 0) return NB_OK;
+  if (plan->S.total_blocks == 0) return NB_OK;
   NB_HIP_CHECK(hipGraphLaunch(plan->exec, reinterpret_cast<hipStream_t>(stream)));
   return NB_OK;
 }
 
 int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out) {
   if (!plan || !out) return fail(NB_EINVAL, "NULL argument");
-  out->tile_rows = plan->tile_blocks * (64 / plan->S.lpr) * kRowSteps;
-  out->n_items = plan->n_items;
-  out->grid = plan->grid;
+  const int br = (64 / plan->S.lpr) * kRowSteps;
+  const Geometry G = geometry(plan->S, plan->w);
+  out->schedule = plan->w.tile_blocks == 0 ? NB_SCHEDULE_STATIC : NB_SCHEDULE_DYNAMIC;
+  out->tile_rows = plan->w.tile_blocks == 0
+                       ? (int32_t)std::min<int64_t>(INT32_MAX, (plan->S.total_blocks + G.grid - 1) / G.grid * br)
+                       : plan->w.tile_blocks * br;
+  out->n_items = plan->w.tile_blocks == 0 ? G.grid : plan->w.n_items();
+  out->grid = G.grid;
   out->tuned = plan->tuned;
   out->n_files = plan->S.n_files;
-  out->rows_per_block = (64 / plan->S.lpr) * kRowSteps;
+  out->rows_per_block = br;
   out->lds_bytes = (int32_t)plan->S.lds;
-  out->reserved = 0;
   return NB_OK;
 }
 

@@ -80,6 +80,8 @@ struct GroupLaunch {
   int32_t grid = 0;
   int32_t n_items = 0;
   int32_t n_groups = 0;
+  bool is_static = true;
+  int64_t total_blocks = 0;
   size_t blob_bytes = 0;
 };
 int prepare_group_launch(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,

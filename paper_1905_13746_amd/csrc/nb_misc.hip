@@ -30,15 +30,40 @@ __device__ __forceinline__ uint32_t e4m3_from_count(uint32_t v) {
   return ((uint32_t)(e + 7) << 3) | (q & 7u);
 }
 
+// The encoding is a byte-to-byte map: each workgroup builds its 256-entry
+// table in LDS, then every lane maps 16 bytes of one row (one chunk) per
+// step; chunks are numbered row by row so a wave covers 1 KB of a row.
+// Rows whose pointers allow 4-byte access go through 16-byte loads and
+// stores; the chunk holding a row's ragged end and every chunk of
+// unaligned rows go byte by byte (never writing past F).
 __global__ __launch_bounds__(256) void quantize_fp8_kernel(const uint8_t* __restrict__ x, int64_t n, int F,
                                                           int64_t ld_x, uint8_t* __restrict__ out,
-                                                          int64_t ld_out) {
-  const int64_t total = n * (int64_t)F;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / F, f = i - r * F;
-    const uint32_t v = min((uint32_t)x[r * ld_x + f], 240u);
-    out[r * ld_out + f] = (uint8_t)e4m3_from_count(v);
+                                                          int64_t ld_out, int vec) {
+  __shared__ uint8_t lut[256];
+  lut[threadIdx.x] = (uint8_t)e4m3_from_count(min((uint32_t)threadIdx.x, 240u));
+  __syncthreads();
+  const int64_t cpr = (F + 15) / 16;                  // chunks per row
+  const int64_t total = n * cpr;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = c / cpr;
+    const int f0 = (int)(c - r * cpr) * 16;
+    const uint8_t* src = x + r * ld_x + f0;
+    uint8_t* dst = out + r * ld_out + f0;
+    if (vec && f0 + 16 <= F) {
+      const dev::u32x4 v = dev::load16(src);
+      dev::u32x4 o;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t u = v[d];
+        o[d] = (uint32_t)lut[u & 0xFFu] | ((uint32_t)lut[(u >> 8) & 0xFFu] << 8) |
+               ((uint32_t)lut[(u >> 16) & 0xFFu] << 16) | ((uint32_t)lut[u >> 24] << 24);
+      }
+      reinterpret_cast<dev::u32x4_a4*>(dst)->v = o;
+    } else {
+      const int m = min(16, F - f0);
+      for (int b = 0; b < m; ++b) dst[b] = lut[src[b]];
+    }
   }
 }
 
@@ -75,10 +100,12 @@ int nb_quantize_fp8(const uint8_t* x, int64_t n, int32_t F, int64_t ld_x, uint8_
   if (n == 0) return NB_OK;
   if (!x || !out) return fail(NB_EINVAL, "NULL argument");
   if (ld_x < F || ld_out < F) return fail(NB_EINVAL, "strides must be >= n_features");
-  const int64_t total = n * (int64_t)F;
-  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  const int64_t chunks = n * ((F + 15) / 16);
+  const int64_t blocks = std::min<int64_t>((chunks + 255) / 256, 8192);
+  const int vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 3) == 0 &&
+                  ld_x % 4 == 0 && ld_out % 4 == 0;
   hipLaunchKernelGGL(quantize_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                     reinterpret_cast<hipStream_t>(stream), x, n, F, ld_x, out, ld_out);
+                     reinterpret_cast<hipStream_t>(stream), x, n, F, ld_x, out, ld_out, vec);
   NB_HIP_CHECK(hipGetLastError());
   return NB_OK;
 }

@@ -45,6 +45,7 @@ struct ScoreMArgs {
   float* log_post;
   float* scores;
   int32_t F, Fp, C, ns;     // ns: rows used (C, or C + 1 with the aux row)
+  int64_t nfast;            // staged kernel: leading wave tiles with every row and load in bounds
 };
 
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
@@ -369,6 +370,211 @@ __global__ __launch_bounds__(kThreadsFull) void scoreM_full_kernel(ScoreMArgs a)
   }
 }
 
+// Staged variant for one column tile (at most 16 score rows) and Fp <= 4096:
+// the feature loads read whole 128-byte lines (a wave instruction covers 8
+// files x 128 bytes) instead of the A-operand layout's 16 files x 64 bytes,
+// and each wave transposes its loads through a private LDS stage into the
+// operand layout.  LDS holds the whole BF16 table (16 rows x Fp, no padding:
+// the 16-byte granules of row r are XOR-swizzled by r, so the 16 rows read
+// by one B fragment fall in distinct banks) plus one 4 KB stage per wave:
+// 32 files x 128 bytes, granule p of file r stored at p ^ ((r >> 1) & 7),
+// which keeps both the line-shaped writes and the operand-shaped reads free
+// of bank conflicts.  Loads run NB_STAGE_DEPTH groups ahead in registers.
+#define NB_STAGE_DEPTH 3
+constexpr int kStageWaves = 8;
+constexpr int kStageThreads = 64 * kStageWaves;
+constexpr int kStageFiles = 32;                   // files per wave tile (two 16-file MFMA tiles)
+constexpr int kStageGB = 128;                     // features per group (two 64-feature windows)
+constexpr int kStageBytes = kStageFiles * kStageGB;
+constexpr int kStageDepth = NB_STAGE_DEPTH;
+#ifndef NB_USE_STAGE
+#define NB_USE_STAGE 1
+#endif
+constexpr bool kUseStage = NB_USE_STAGE != 0;
+
+__device__ __forceinline__ int stage_granule(int r, int p) { return r * 8 + (p ^ ((r >> 1) & 7)); }
+
+// Destination of outputs the caller did not request (and of the lanes that
+// hold no label): the fast path stores unconditionally so that the number of
+// memory operations in flight stays known at compile time.
+__device__ int32_t g_stage_sink_label[64];
+__device__ float g_stage_sink_post[64 * 16];
+
+template <int XT, bool BIN>
+__global__ __launch_bounds__(kStageThreads) void scoreM_stage_kernel(ScoreMArgs a) {
+  extern __shared__ __attribute__((aligned(16))) dev::u32x4 lds4[];
+  dev::u32x4* tbl = lds4;                                    // [16][Fp / 8] granules, swizzled
+  const int gpr = a.Fp / 8;                                  // granules per table row
+  // stage the table (rows >= ns are zero)
+  for (int i = threadIdx.x; i < 16 * gpr; i += kStageThreads) {
+    const int r = i / gpr, g = i - r * gpr;
+    dev::u32x4 v = {0u, 0u, 0u, 0u};
+    if (r < a.ns) v = *reinterpret_cast<const dev::u32x4*>(a.rows16 + (int64_t)r * a.Fp + 8 * g);
+    tbl[r * gpr + (g ^ r)] = v;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  dev::u32x4* stg = lds4 + 16 * gpr + wave * (kStageBytes / 16);
+  const int col = lane & 15, q = lane >> 4;
+  const int64_t ld = a.ld_bytes;
+  const int64_t wave_id = (int64_t)blockIdx.x * kStageWaves + wave;
+  const int64_t nwaves = (int64_t)gridDim.x * kStageWaves;
+  const int ngroups = (a.F + kStageGB - 1) / kStageGB;
+  const float bias = (col < a.ns) ? a.row_bias[col] : 0.0f;
+  // load lane layout: instruction j covers files 8j + (lane >> 3), granule lane & 7
+  const int lr = lane >> 3, lp = lane & 7;
+  uint32_t rel[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) rel[j] = (uint32_t)((8 * j + lr) * ld) + 16 * lp;
+  int wpos[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) wpos[j] = stage_granule(8 * j + lr, lp);
+  // operand lane layout: tile mt, window u -> file 16 mt + col, granule 4 u + q
+  int rpos[2][2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) rpos[mt][u] = stage_granule(16 * mt + col, 4 * u + q);
+
+  f32x4 acc[2][1];
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) acc[mt][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  };
+  // transpose one group through the stage and multiply it into acc
+  auto compute_group = [&](int g, const dev::u32x4 (&src)[4]) {
+    // the previous group's operand reads are done before the stage is
+    // rewritten: LDS operations of a wave complete in order
+#pragma unroll
+    for (int j = 0; j < 4; ++j) stg[wpos[j]] = src[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int f0 = g * kStageGB + u * kWindow;         // first feature of the window
+      dev::u32x4 av[2][2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        dev::u32x4 xv = stg[rpos[mt][u]];
+        if (XT == NB_X_FP8 && f0 + 16 * q + 16 > a.F) {   // NaN encodings past the last feature
+          const int nv = max(0, a.F - (f0 + 16 * q));
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const int nb = min(4, max(0, nv - 4 * d));
+            xv[d] &= (nb >= 4) ? ~0u : ((1u << (8 * nb)) - 1u);
+          }
+        }
+        to_bf16<XT, BIN>(xv, av[mt][0], av[mt][1]);
+      }
+      const int G = (f0 + 16 * q) / 8;                    // table granule of this lane's k-group
+      const dev::u32x4 b0 = tbl[col * gpr + (G ^ col)];
+      const dev::u32x4 b1 = tbl[col * gpr + ((G + 1) ^ col)];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        acc[mt][0] = mfma(av[mt][0], b0, acc[mt][0]);
+        acc[mt][0] = mfma(av[mt][1], b1, acc[mt][0]);
+      }
+    }
+  };
+  // Fast epilogue: 16 classes in the 16 columns, every row present, every
+  // store issued (to a sink when the output was not requested).
+  const bool want_lab = a.labels != nullptr, want_lp = a.log_post != nullptr;
+  auto finish_fast = [&](int64_t row0) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + 16 * mt + 4 * q + i;
+        const float sv = acc[mt][0][i] + bias;
+        float m = sv;
+        int best = col;
+#pragma unroll
+        for (int sh = 1; sh < 16; sh <<= 1) {
+          const float om = __shfl_xor(m, sh);
+          const int ob = __shfl_xor(best, sh);
+          if (om > m || (om == m && ob < best)) {
+            m = om;
+            best = ob;
+          }
+        }
+        float z = __expf(sv - m);
+#pragma unroll
+        for (int sh = 1; sh < 16; sh <<= 1) z += __shfl_xor(z, sh);
+        const float lse = m + __logf(z);
+        int32_t* pl = (want_lab && col == 0) ? a.labels + row : g_stage_sink_label + lane;
+        float* pp = want_lp ? a.log_post + row * 16 + col : g_stage_sink_post + lane;
+        *pl = best;
+        *pp = sv - lse;
+      }
+    }
+  };
+
+  // ---- full tiles [0, a.nfast): one pipelined stream of (tile, group)
+  // units; loads run kStageDepth - 1 units ahead and cross tile boundaries.
+  // The prefetch past the last unit re-reads the last unit (an L2 hit).
+  const int my_tiles = (a.nfast > wave_id) ? (int)((a.nfast - wave_id + nwaves - 1) / nwaves) : 0;
+  const int units = my_tiles * ngroups;
+  auto issue = [&](int k, dev::u32x4 (&dst)[4]) {
+    k = min(k, units - 1);
+    const int it = k / ngroups, g = k - it * ngroups;
+    const int64_t wbase = (wave_id + (int64_t)it * nwaves) * kStageFiles * ld + (int64_t)g * kStageGB;
+    const auto rsrc = dev::make_rsrc(a.x + wbase, a.total_bytes - wbase);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[j] = dev::buffer_load16(rsrc, rel[j]);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  int cg = 0, ct = 0;
+  auto consume = [&](const dev::u32x4 (&src)[4]) {
+    compute_group(cg, src);
+    if (++cg == ngroups) {
+      finish_fast((wave_id + (int64_t)ct * nwaves) * kStageFiles);
+      zero_acc();
+      cg = 0;
+      ++ct;
+    }
+  };
+  zero_acc();
+  if (units > 0) {
+    static_assert(kStageDepth == 3, "the unit loop below is written for three register buffers");
+    dev::u32x4 b0[4], b1[4], b2[4];
+    issue(0, b0);
+    issue(1, b1);
+    for (int k = 0;; k += 3) {
+      issue(k + 2, b2);
+      consume(b0);
+      if (k + 1 >= units) break;
+      issue(k + 3, b0);
+      consume(b1);
+      if (k + 2 >= units) break;
+      issue(k + 4, b1);
+      consume(b2);
+      if (k + 3 >= units) break;
+    }
+  }
+
+  // ---- remaining tiles: guarded loads, partial rows, generic epilogue
+  const int64_t nwtile = (a.n + kStageFiles - 1) / kStageFiles;
+  for (int64_t wt = a.nfast + wave_id; wt < nwtile; wt += nwaves) {
+    const int64_t row0 = wt * kStageFiles;
+    zero_acc();
+    for (int g = 0; g < ngroups; ++g) {
+      dev::u32x4 v[4];
+      const int64_t wbase = row0 * ld + (int64_t)g * kStageGB;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[j] = dev::u32x4{0u, 0u, 0u, 0u};
+        const int64_t off = wbase + rel[j];
+        if (row0 + 8 * j + lr < a.n) v[j] = dev::load16_guarded(a.x + off, a.total_bytes - off);
+      }
+      compute_group(g, v);
+    }
+    epilogue<1, 2>(a, acc, lane, row0);
+  }
+}
+
 using KernelFn = void (*)(ScoreMArgs);
 
 // column tiles rounded up to a compiled width (extra columns are zero rows)
@@ -438,6 +644,31 @@ int launch_scoreC_mfma(const nb_model* m, const nb_layout& L, const void* x, int
   const int64_t files = (int64_t)16 * mt;
   if (files * kWavesFull * a.ld_bytes >= ((int64_t)1 << 31))
     return fail(NB_EINVAL, "row stride too large (a tile of rows must span < 2 GiB)");
+  const size_t lds_stage = (size_t)16 * L.padded_features * sizeof(uint16_t) + (size_t)kStageWaves * kStageBytes;
+  if (ntr == 1 && C == 16 && !scores && kUseStage && lds_stage <= (size_t)max_lds_per_block()) {
+    if ((int64_t)kStageFiles * a.ld_bytes >= ((int64_t)1 << 31))
+      return fail(NB_EINVAL, "row stride too large (a tile of rows must span < 2 GiB)");
+    {
+      // leading tiles whose rows all exist and whose group loads stay in the buffer
+      const int64_t span = (int64_t)((a.F + kStageGB - 1) / kStageGB) * kStageGB;
+      const int64_t full = n / kStageFiles;
+      const int64_t rmax = (a.total_bytes >= span) ? (a.total_bytes - span) / a.ld_bytes : -1;
+      a.nfast = std::max<int64_t>(0, std::min(full, (rmax + 1) / kStageFiles));
+    }
+    const void* sf = (xtype == NB_X_U8) ? (bin ? reinterpret_cast<const void*>(scoreM_stage_kernel<NB_X_U8, true>)
+                                                : reinterpret_cast<const void*>(scoreM_stage_kernel<NB_X_U8, false>))
+                                        : (bin ? reinterpret_cast<const void*>(scoreM_stage_kernel<NB_X_FP8, true>)
+                                                : reinterpret_cast<const void*>(scoreM_stage_kernel<NB_X_FP8, false>));
+    NB_HIP_CHECK(hipFuncSetAttribute(sf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_stage));
+    const int64_t nwtile = (n + kStageFiles - 1) / kStageFiles;
+    const int64_t want = (nwtile + kStageWaves - 1) / kStageWaves;
+    const int64_t cap = (int64_t)resident_per_cu(sf, kStageThreads, lds_stage) * device_cu_count();
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
+    void* args[] = {&a};
+    NB_HIP_CHECK(hipLaunchKernel(sf, dim3(grid), dim3(kStageThreads), args, lds_stage, s));
+    NB_HIP_CHECK(hipGetLastError());
+    return NB_OK;
+  }
   if (full) {
     NB_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_full));

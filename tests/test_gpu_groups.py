@@ -114,8 +114,8 @@ def test_groups_other_shapes(F, xdtype, fp8):
 def test_tile_invariance():
     _case("groups tile invariance")
     models, _, gmodel, xs, _, _ = _build(2000, nb.MULTINOMIAL)
-    ref = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True)
-    for tile in (1, 8, 40, 1000, 1 << 20):
+    ref = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True)      # static ranges
+    for tile in (1, 8, 40, 1000, 1 << 20):                                  # dynamic items
         got = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True, tile_rows=tile)
         torch.cuda.synchronize()
         for a, b in zip(ref, got):
@@ -129,6 +129,7 @@ def test_plan_graph_replays_equal_eager():
     plan = nbg.GroupPlan(models, list(zip(gmodel, xs)), scores=True)
     info = plan.info()
     assert info["n_files"] == sum(SIZES) and info["n_items"] > 0 and info["grid"] >= 1
+    assert info["schedule"] == "static"
     for rep in range(4):
         for o in plan.outs:
             for t in o:
@@ -144,10 +145,12 @@ def test_plan_graph_replays_equal_eager():
     plan.close()
 
 
-def test_plan_new_data_in_same_buffers():
-    _case("groups plan refill")
+@pytest.mark.parametrize("tile", [0, 64])
+def test_plan_new_data_in_same_buffers(tile):
+    _case(f"groups plan refill tile={tile}")
     models, oms, gmodel, xs, _, route = _build(1000, nb.MULTINOMIAL)
-    plan = nbg.GroupPlan(models, list(zip(gmodel, xs)))
+    plan = nbg.GroupPlan(models, list(zip(gmodel, xs)), tile_rows=tile)
+    assert plan.info()["schedule"] == ("static" if tile == 0 else "dynamic")
     for step in range(2):
         for g, x in enumerate(xs):
             if x.shape[0]:

@@ -135,3 +135,52 @@ def test_more_classes_than_vector_path_rejected():
     with pytest.raises(nbg.NBError):
         nbg.score(m, X)                      # FP32 table, 40 classes
     nbg.score(m, X, wtype=nbg.W_BF16)        # matrix cores take it
+
+
+# Sixteen classes with labels and log posteriors only take the staged
+# matrix-core kernel (whole-line loads transposed through LDS).
+STAGED = [(4096, 3000), (1000, 1), (1000, 31), (1000, 33), (129 * 4, 777), (4, 100), (4000, 257), (2048, 4097)]
+
+
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+@pytest.mark.parametrize("F,n", STAGED, ids=[f"F{f}_n{n}" for f, n in STAGED])
+def test_bf16_staged_matrix_core_path(F, n, kind):
+    _case(f"bf16 staged mfma F={F} n={n} {kind}")
+    wl = family(16, F)
+    m, om = _train(wl, 5000, kind)
+    Xt, _ = wl.test_set(n, device=DEV)
+    lab, lp, _ = nbg.score(m, Xt, wtype=nbg.W_BF16)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(Xt), to_np(lab), to_np(lp), None, wtype=nbg.W_BF16)
+    lab1, _, _ = nbg.score(m, Xt, wtype=nbg.W_BF16, log_post=False)
+    torch.cuda.synchronize()
+    assert torch.equal(lab1, lab)
+
+
+def test_staged_fp8_and_strided():
+    _case("bf16 staged mfma fp8 + strided")
+    F, n, ld = 1000, 1301, 1040
+    wl = family(16, F)
+    m, om = _train(wl, 5000, nb.MULTINOMIAL)
+    X, _ = wl.test_set(n, device=DEV)
+    q8 = W.to_fp8_e4m3(X)
+    lab, lp, _ = nbg.score(m, q8, wtype=nbg.W_BF16, fp8=True)
+    torch.cuda.synchronize()
+    assert_scores(om, P.e4m3_value(to_np(q8)), to_np(lab), to_np(lp), None, wtype=nbg.W_BF16, xtype=X_FP8)
+    big = torch.zeros((n, ld), dtype=torch.uint8, device=DEV)
+    big[:, :F] = X
+    lab2, lp2, _ = nbg.score(m, big[:, :F], wtype=nbg.W_BF16)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(X), to_np(lab2), to_np(lp2), None, wtype=nbg.W_BF16)
+
+
+def test_staged_batch_invariance():
+    wl = family(16, 1000)
+    m, _ = _train(wl, 5000, nb.MULTINOMIAL)
+    X, _ = wl.test_set(5000, device=DEV)
+    full = nbg.score(m, X, wtype=nbg.W_BF16)
+    for a, b in ((0, 1), (100, 229), (31, 4097), (4990, 5000)):
+        part = nbg.score(m, X[a:b], wtype=nbg.W_BF16)
+        for u, v in zip(full, part):
+            if u is not None:
+                assert torch.equal(u[a:b], v)

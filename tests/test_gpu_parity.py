@@ -129,6 +129,14 @@ def test_quantize_kernel_bit_exact():
     assert (got == want).all()
     X, _ = W.binary_u8(500).test_set(999, device=DEV)
     assert (to_np(nbg.quantize_fp8(X)) == P.quantize_fp8(to_np(X))[0]).all()
+    # ragged row ends, unaligned rows (byte path) and strided outputs
+    for F, off in ((1001, 0), (37, 0), (100, 1), (16, 3)):
+        base = torch.randint(0, 256, (300 * 1040 + 8,), dtype=torch.uint8, device=DEV)
+        xv = base[off: off + 299 * 1040 + F].as_strided((300, F), (1040, 1))
+        out = torch.full((300, 1048), 7, dtype=torch.uint8, device=DEV)
+        nbg.quantize_fp8(xv, out=out[:, :F])
+        assert (to_np(out[:, :F]) == P.quantize_fp8(to_np(xv))[0]).all()
+        assert (to_np(out[:, F:]) == 7).all()            # nothing written past F
 
 
 @pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])

@@ -50,7 +50,7 @@ METRIC = "files scored/sec and HBM GB/s (% peak) at F=1000; reduced-prec vs FP32
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--features", type=int, default=1000)
     ap.add_argument("--n-train", type=int, default=200_000)
@@ -270,8 +270,12 @@ def groups_leg(nbg, W, steps: int = 20):
     return res
 
 
-def serve_leg(nbg, W, n_requests: int = 8000):
-    """Continuous-batching server on the 8-model request mix."""
+def serve_leg(nbg, W, n_requests: int = 8000, full: bool = False):
+    """Continuous-batching server on the 8-model request mix.  full: the
+    whole sweep (0.1 .. 1.2 of saturation plus fixed rates) at 20,000
+    requests per point; otherwise three load points at 8,000 requests."""
+    if full:
+        n_requests = 20_000
     models, pools_h, pools_d = [], [], []
     for m in range(8):
         wl = W.serve_model_workload(m)
@@ -312,14 +316,20 @@ def serve_leg(nbg, W, n_requests: int = 8000):
                        "n = floor(exp(U(0, ln 4097))); models uniform; Poisson arrivals; latency = arrival -> "
                        "labels and log posteriors in pinned host memory; 4 streams, <= 64 requests per batch, "
                        "1 GiB arena"}
+    fracs = (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2) if full else (0.25, 0.5, 0.9)
+    fixed = (1_000, 3_000, 10_000, 30_000, 100_000) if full else ()
     for mode, dev in (("host_inputs", False), ("device_inputs", True)):
         sat = run(*trace(float("inf")), dev)
         res = {"saturation": sat}
-        for frac in (0.25, 0.5, 0.9):
+        for frac in fracs:
             qps = frac * sat["req_per_s"]
             r = run(*trace(qps), dev)
             r["offered_req_per_s"] = qps
             res[f"load_{frac}"] = r
+        for qps in fixed:
+            r = run(*trace(float(qps)), dev)
+            r["offered_req_per_s"] = qps
+            res[f"rate_{qps}"] = r
         out[mode] = res
     return out
 
@@ -352,7 +362,8 @@ def main():
         if args.leg == "precision":
             res = precision_compare(nbg, W, fill=args.fill_inputs)
         else:
-            res = {"f_sweep": f_sweep, "groups": groups_leg, "serve": serve_leg}[args.leg](nbg, W)
+            res = {"f_sweep": f_sweep, "groups": groups_leg,
+                   "serve": lambda a, b: serve_leg(a, b, full=True)}[args.leg](nbg, W)
         print(json.dumps({"leg": args.leg, **res}), flush=True)
         return
 

@@ -173,9 +173,12 @@ int nb_route_groups(const int64_t* class_counts_host, int32_t n_groups, int32_t 
  * persistent kernel launch over the concatenation of the groups' files;
  * each file's results are bit-identical to nb_score of its group alone
  * (same summation order), whatever the schedule, tile or grid.
- * Schedules: static ranges (each workgroup scores an equal contiguous run
- * of files, staging a group's table in LDS when its run enters that group)
- * or dynamic items (groups cut into tiles of tile_rows files, taken largest
+ * Schedules: stream (the default when NS x Fp <= 2048 table floats: groups
+ * cut into items of a few blocks, taken round-robin in memory order, each
+ * wave's loads pipelined across items, the next item's table loaded with
+ * them), static ranges (each workgroup scores an equal contiguous run of
+ * files, staging a group's table in LDS when its run enters that group), or
+ * dynamic items (groups cut into tiles of tile_rows files, taken largest
  * first from a device counter).
  *
  * One group of files (device pointers as for nb_score): */
@@ -193,8 +196,8 @@ typedef struct {
 /* Requirements: every model a group uses has two classes, and all of them
  * share the kind and the feature count F (the paper keeps k features per
  * group).  Each non-empty group needs at least one output.
- * tile_rows: 0 = static ranges; > 0 = dynamic items of that many files
- * (rounded up to whole blocks of the kernel).
+ * tile_rows: 0 = the default schedule (stream, else static ranges); > 0 =
+ * dynamic items of that many files (rounded up to whole blocks).
  * Errors: NB_EINVAL (arguments, per group), NB_ENOMODEL (every model is -1),
  * NB_ENOMEM (workspace too small), NB_EHIP. */
 
@@ -217,25 +220,30 @@ int nb_score_groups(const nb_model* models, int32_t n_models, const nb_group* gr
  * Launches of one plan must not overlap (they share the work counter).
  * Schedule choice (tile_rows == 0): one recorded for the same shape (kept
  * in memory, and in the JSON file named by the NB_TUNE_CACHE environment
- * variable when set), else with NB_PLAN_TUNE the fastest of static ranges
- * and several dynamic tiles, timed on the caller's data (this scores the
- * groups, writing the outputs, a few times), else static ranges.
+ * variable when set), else with NB_PLAN_TUNE the fastest of the stream at
+ * several item sizes, static ranges and several dynamic tiles, timed on the
+ * caller's data (this scores the groups, writing the outputs, a few
+ * times), else the default schedule.
  * tile_rows > 0 fixes dynamic items of that size. */
 typedef struct nb_group_plan nb_group_plan;
-#define NB_PLAN_TUNE 1
+#define NB_PLAN_TUNE   1
+#define NB_PLAN_STATIC 2  /* force static ranges (tile_rows ignored)           */
+#define NB_PLAN_STREAM 4  /* force the stream, items of tile_rows files (0: the
+                             default size); NB_EINVAL if the table is too big */
 
 #define NB_SCHEDULE_STATIC  0
 #define NB_SCHEDULE_DYNAMIC 1
+#define NB_SCHEDULE_STREAM  2
 
 typedef struct {
   int32_t tile_rows;       /* files per workgroup run (static) or full item    */
-  int32_t n_items;         /* runs (static) or items (dynamic) of one launch   */
+  int32_t n_items;         /* runs (static) or items (stream, dynamic)         */
   int32_t grid;            /* workgroups launched                              */
   int32_t tuned;           /* 0 default or caller's tile, 1 timed, 2 cached    */
   int64_t n_files;         /* files scored per launch                          */
   int32_t rows_per_block;  /* files per wave block of the kernel               */
   int32_t lds_bytes;       /* table bytes staged in LDS per workgroup          */
-  int32_t schedule;        /* NB_SCHEDULE_STATIC or NB_SCHEDULE_DYNAMIC        */
+  int32_t schedule;        /* NB_SCHEDULE_STATIC, _DYNAMIC or _STREAM          */
 } nb_group_plan_info;
 
 int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,

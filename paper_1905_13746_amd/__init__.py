@@ -246,14 +246,19 @@ class GroupPlan:
     of the one persistent launch); launch() replays it."""
 
     def __init__(self, models, groups, wtype: int = W_F32, fp8: bool = False, labels=True, log_post=True,
-                 scores=False, tile_rows: int = 0, tune: bool = False, outs=None, stream=None):
+                 scores=False, tile_rows: int = 0, tune: bool = False, schedule: str | None = None, outs=None,
+                 stream=None):
+        """schedule: None (tile_rows > 0: dynamic items; else tuned or the
+        default), "static" or "stream" (items of tile_rows files)."""
         lib = load()
         self._lib = lib
         self.call = _GroupCall(models, groups, fp8, labels, log_post, scores, outs)
         cm, nm, cg, ng, xt = self.call.args()
+        flags = (_lib.PLAN_TUNE if tune else 0) | {None: 0, "static": _lib.PLAN_STATIC,
+                                                   "stream": _lib.PLAN_STREAM}[schedule]
         h = ctypes.c_void_p()
-        check(lib.nb_group_plan_create(cm, nm, cg, ng, xt, int(wtype), int(tile_rows),
-                                       _lib.PLAN_TUNE if tune else 0, _stream(stream), ctypes.byref(h)),
+        check(lib.nb_group_plan_create(cm, nm, cg, ng, xt, int(wtype), int(tile_rows), flags, _stream(stream),
+                                       ctypes.byref(h)),
               "nb_group_plan_create")
         self.handle = h
 
@@ -268,7 +273,7 @@ class GroupPlan:
         inf = _lib.NbGroupPlanInfo()
         check(self._lib.nb_group_plan_query(self.handle, ctypes.byref(inf)), "nb_group_plan_query")
         d = {k: getattr(inf, k) for k, _ in inf._fields_}
-        d["schedule"] = "static" if d["schedule"] == 0 else "dynamic"
+        d["schedule"] = ("static", "dynamic", "stream")[d["schedule"]]
         return d
 
     def close(self):

@@ -20,7 +20,7 @@ MULTINOMIAL, BERNOULLI = 0, 1
 X_U8, X_I32, X_FP8 = 0, 1, 2
 W_F32, W_BF16 = 0, 1
 TRAIN_ASYNC = 1
-PLAN_TUNE = 1
+PLAN_TUNE, PLAN_STATIC, PLAN_STREAM = 1, 2, 4
 SERVE_DEVICE_INPUTS, SERVE_SIMULATE = 1, 2
 
 

@@ -47,6 +47,36 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, in
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
 }
 
+// Values the compiler cannot prove wave-uniform (they pass through loop-
+// carried state) but are: take lane 0's copy, so descriptors built from
+// them live in scalar registers instead of forcing per-lane loops.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  return reinterpret_cast<T*>(uniform64(reinterpret_cast<int64_t>(p)));
+}
+
+// Load of read-only data at a wave-uniform address through the constant
+// address space: a scalar load (lgkmcnt), where a plain load could become a
+// vector load (vmcnt, ordered behind the streaming loads in flight) when
+// the compiler cannot rule out that the kernel's own stores alias it.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  typedef const __attribute__((address_space(4))) uint32_t* ConstWords;
+  const ConstWords q = (ConstWords)(p);
+  uint32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = q[i];
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
+
 // Cache policy of the streaming feature loads (gfx940+ bits: 1 sc0, 2 nt,
 // 16 sc1); non-temporal by default: each feature byte is read once.
 #ifndef NB_STREAM_CPOL

@@ -52,13 +52,213 @@ static_assert(sizeof(Score2Args) <= kGroupDescBound, "descriptor bound used by s
 
 struct GroupsArgs {
   const Score2Args* descs;   // [n_groups]
-  const GroupItem* items;    // dynamic: [n_items], largest first
+  const GroupItem* items;    // dynamic: [n_items], largest first; stream: fast items in memory order
+  const GroupItem* tails;    // stream: [n_tails] blocks needing guarded loads
   const int64_t* gstart;     // static: [n_groups + 1] first block of each group
   int32_t* counter;          // dynamic: [2] next item, finished workgroups
   int32_t n_items;
+  int32_t n_tails;
   int32_t n_groups;
+  int32_t Fp;                // padded feature count (every group's model has the same F)
+  int32_t nch;               // feature chunks per row
   int64_t total_blocks;
 };
+
+// ---- stream schedule (tables of at most kStreamTable floats: NS * Fp)
+// Workgroup w takes the fast items w, w + grid, ... in memory order, so the
+// whole machine sweeps one window of the concatenated files, as the
+// single-model kernel does.  Every item holds at least four blocks, so each
+// wave has work in every item.  A wave's (item, block, chunk) units form ONE
+// pipelined sequence across items: the loads of the next unit are in flight
+// while the current one is accumulated, item boundaries included.  The next
+// item's scoring rows ride along: when a wave issues an item's first unit it
+// also loads its eighth of that item's table (kStreamTPL floats per lane);
+// when it consumes that unit it writes them to one of two LDS table buffers
+// and meets the other waves at an LDS-only barrier (no wait on the feature
+// loads in flight).  Buffer k % 2 is free again because every wave passed
+// item k - 1's barrier after finishing item k - 2.  The blocks that need
+// guarded loads (each group's ragged end) are scored after the stream.
+constexpr int kStreamTable = 2048;
+constexpr int kStreamTPL = kStreamTable / kThreads;     // 8 floats per lane
+
+// Workgroup barrier for LDS data only: the wavefront-scope fences keep the
+// compiler from moving memory accesses across it without emitting waits,
+// lgkmcnt(0) completes this wave's LDS writes, and nothing waits for the
+// global loads in flight (a workgroup-scope fence would).
+__device__ __forceinline__ void lds_only_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt untouched
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+__global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsArgs g) {
+  constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
+  constexpr int NV = EB;
+  constexpr int G = 64 / LPR;
+  constexpr int R = kRowSteps;
+  constexpr int BR = G * R;
+  constexpr int CW = 16 * LPR;
+  constexpr int TPL = kStreamTPL;
+  __shared__ __attribute__((aligned(16))) float tbl2[2][kStreamTable];
+  __shared__ __attribute__((aligned(16))) float tbl_sink[kStreamTable];
+  __shared__ float stage[kWaves][NS][BR];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sub = lane / LPR, j = lane % LPR;
+  const int nch = MULTI ? g.nch : 1;
+  const int Fp = g.Fp;
+  const int grid = (int)gridDim.x;
+  const int my_items = (g.n_items > (int)blockIdx.x) ? (g.n_items - (int)blockIdx.x + grid - 1) / grid : 0;
+
+  float acc[R][NS];
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+  };
+  zero_acc();
+  float w[NS][16];
+  uint32_t keep[4] = {~0u, ~0u, ~0u, ~0u};
+
+  if (my_items > 0) {
+    // ---- issue side: the item whose unit is being loaded
+    int ik = 0, ib = 0, ich = 0;
+    bool at_end = false;
+    GroupItem iit = dev::load_uniform(g.items + blockIdx.x);
+    Score2Args ia = dev::load_uniform(g.descs + iit.group);
+    int i_nbw = (iit.nblocks - wave + kWaves - 1) / kWaves;
+    uint32_t voff[R];
+    auto set_voff = [&](int64_t ld) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) voff[i] = (uint32_t)((i * G + sub) * ld) + (uint32_t)(16 * j * EB);
+    };
+    set_voff(ia.ld_bytes);
+    auto advance = [&]() {
+      if (at_end) return;
+      if (++ich < nch) return;
+      ich = 0;
+      if (++ib < i_nbw) return;
+      if (ik + 1 >= my_items) {            // stay on the last unit: it is re-issued (an L2 hit)
+        ib = i_nbw - 1;
+        ich = nch - 1;
+        at_end = true;
+        return;
+      }
+      ++ik;
+      ib = 0;
+      iit = dev::load_uniform(g.items + blockIdx.x + ik * grid);
+      ia = dev::load_uniform(g.descs + iit.group);
+      i_nbw = (iit.nblocks - wave + kWaves - 1) / kWaves;
+      set_voff(ia.ld_bytes);
+    };
+    auto issue = [&](dev::u32x4 (&dst)[R][NV], dev::u32x4 (&tdst)[2]) {
+      const int64_t blk = iit.block0 + wave + (int64_t)ib * kWaves;
+      const int64_t off = blk * BR * ia.ld_bytes + (int64_t)ich * CW * EB;
+      const auto rsrc = dev::make_rsrc(dev::uniform_ptr(ia.x + off), dev::uniform64(ia.total_bytes - off));
+      // this lane's share of the item's table: floats [TPL*tid, +TPL) of
+      // the [NS][Fp] rows (FP32: 32 bytes; BF16: 16 bytes, second load
+      // empty).  Units other than an item's first load from an empty range:
+      // no memory access, the same number of loads in flight.
+      const bool bf = __builtin_amdgcn_readfirstlane(ia.wt) == NB_W_BF16;
+      const int tbytes = __builtin_amdgcn_readfirstlane((ib == 0 && ich == 0) ? NS * Fp * (bf ? 2 : 4) : 0);
+      const auto trs =
+          dev::make_rsrc(dev::uniform_ptr(bf ? (const void*)ia.rows16 : (const void*)ia.rows32), tbytes);
+      const uint32_t toff = (uint32_t)threadIdx.x * TPL * (bf ? 2u : 4u);
+      tdst[0] = dev::buffer_load16(trs, toff);
+      tdst[1] = dev::buffer_load16(trs, bf ? (uint32_t)tbytes : toff + 16u);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, voff[i] + 16 * q);
+      __builtin_amdgcn_sched_barrier(0);
+      advance();
+    };
+
+    // ---- consume side
+    int ck = 0, cb = 0, cch = 0;
+    GroupItem cit = iit;
+    Score2Args ca = ia;
+    int c_nbw = i_nbw;
+    float rb[NS];
+    bool done = false;
+    auto consume = [&](dev::u32x4 (&src)[R][NV], const dev::u32x4 (&tsrc)[2]) {
+      float* tb = tbl2[ck & 1];
+      // every unit consumes its table registers the same way (the first unit
+      // of an item into the item's buffer, the others into a sink), so the
+      // registers are free after the write on every path
+      const bool first = cb == 0 && cch == 0;
+      const bool bf = __builtin_amdgcn_readfirstlane(ca.wt) == NB_W_BF16;
+      float tv[TPL];
+#pragma unroll
+      for (int e = 0; e < TPL; ++e) {
+        const uint32_t word = tsrc[0][e >> 1];
+        const float from16 = __uint_as_float((e & 1) ? (word & 0xFFFF0000u) : (word << 16));
+        const float from32 = __uint_as_float(tsrc[e >> 2][e & 3]);
+        tv[e] = bf ? from16 : from32;
+      }
+      float4* t4 = reinterpret_cast<float4*>((first ? tb : tbl_sink) + threadIdx.x * TPL);
+      t4[0] = make_float4(tv[0], tv[1], tv[2], tv[3]);
+      t4[1] = make_float4(tv[4], tv[5], tv[6], tv[7]);
+      if (first) {                                       // first unit of item ck
+        lds_only_barrier();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) rb[s] = dev::load_uniform(ca.row_bias + s);
+        if (!MULTI) {
+          load_table<XT, NS>(tb, Fp, 16 * j, w);
+          if (XT == NB_X_FP8) fp8_keep_mask(ca.F, 16 * j, keep);
+        }
+      }
+      if (MULTI) {
+        const int fc = cch * CW + 16 * j;
+        load_table<XT, NS>(tb, Fp, fc, w);
+        if (XT == NB_X_FP8) fp8_keep_mask(ca.F, fc, keep);
+      }
+      accumulate_rows<XT, NS, BIN, NV>(src, w, keep, true, acc);
+      if (++cch == nch) {
+        const int64_t row0 = (cit.block0 + wave + (int64_t)cb * kWaves) * BR;
+        finish_block<LPR, NS, true>(ca, acc, lane, wave, sub, rb, row0, BR, stage);
+        zero_acc();
+        cch = 0;
+        if (++cb == c_nbw) {
+          cb = 0;
+          if (++ck >= my_items) {
+            done = true;
+          } else {
+            cit = dev::load_uniform(g.items + blockIdx.x + ck * grid);
+            ca = dev::load_uniform(g.descs + cit.group);
+            c_nbw = (cit.nblocks - wave + kWaves - 1) / kWaves;
+          }
+        }
+      }
+    };
+
+    dev::u32x4 b0[R][NV], b1[R][NV];
+    dev::u32x4 t0[2], t1[2];
+    issue(b0, t0);
+    for (;;) {
+      issue(b1, t1);
+      consume(b0, t0);
+      if (done) break;
+      issue(b0, t0);
+      consume(b1, t1);
+      if (done) break;
+    }
+  }
+
+  // ---- blocks needing guarded loads
+  for (int t = blockIdx.x; t < g.n_tails; t += grid) {
+    const GroupItem it = dev::load_uniform(g.tails + t);
+    const Score2Args a = dev::load_uniform(g.descs + it.group);
+    __syncthreads();
+    stage_table<NS>(a, tbl2[0]);
+    __syncthreads();
+    score_blocks<XT, LPR, NS, BIN, MULTI>(a, tbl2[0], it.block0 + wave, kWaves, it.block0 + it.nblocks, stage);
+  }
+}
 
 template <int XT, int LPR, int NS, bool BIN, bool MULTI>
 __global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsArgs g) {
@@ -73,14 +273,14 @@ __global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsAr
   int lo = 0, hi = g.n_groups - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (g.gstart[mid] <= b) lo = mid;
+    if (dev::load_uniform(g.gstart + mid) <= b) lo = mid;
     else hi = mid - 1;
   }
   for (int gi = lo; b < b1; ++gi) {
-    const int64_t gs = g.gstart[gi];
-    const int64_t seg_end = min(b1, g.gstart[gi + 1]);
+    const int64_t gs = dev::load_uniform(g.gstart + gi);
+    const int64_t seg_end = min(b1, dev::load_uniform(g.gstart + gi + 1));
     if (seg_end <= b) continue;                 // empty group
-    const Score2Args a = g.descs[gi];
+    const Score2Args a = dev::load_uniform(g.descs + gi);
     __syncthreads();                            // the previous group's table is no longer read
     stage_table<NS>(a, tbl);
     __syncthreads();
@@ -101,8 +301,8 @@ __global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g) {
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(s_item);
     if (it >= g.n_items) break;
-    const GroupItem item = g.items[it];
-    const Score2Args a = g.descs[item.group];
+    const GroupItem item = dev::load_uniform(g.items + it);
+    const Score2Args a = dev::load_uniform(g.descs + item.group);
     stage_table<NS>(a, tbl);
     __syncthreads();
     score_blocks<XT, LPR, NS, BIN, MULTI>(a, tbl, item.block0 + wave, kWaves, item.block0 + item.nblocks, stage);
@@ -126,6 +326,13 @@ struct Grouped {
   }
 };
 
+struct GroupedStream {
+  template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+  static const void* fn() {
+    return reinterpret_cast<const void*>(score2_groups_stream_kernel<XT, LPR, NS, BIN, MULTI>);
+  }
+};
+
 struct GroupedStatic {
   template <int XT, int LPR, int NS, bool BIN, bool MULTI>
   static const void* fn() {
@@ -146,7 +353,12 @@ struct GroupSetup {
   size_t lds = 0;
   const void* fn = nullptr;        // dynamic-item kernel
   const void* fn_static = nullptr; // static-range kernel
-  int grid_cap = 1;                // resident workgroups on the device
+  const void* fn_stream = nullptr; // stream kernel (tables of at most kStreamTable floats)
+  int Fp = 0;
+  int grid_cap = 1;                // resident workgroups on the device (dynamic kernel)
+  int grid_cap_static = 1;
+  int grid_cap_stream = 1;
+  bool stream_ok = false;
   int64_t total_blocks = 0;
 };
 
@@ -216,7 +428,14 @@ int setup_groups(const nb_model* models, int32_t n_models, const nb_group* group
     NB_HIP_CHECK(hipFuncSetAttribute(S->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds));
     NB_HIP_CHECK(hipFuncSetAttribute(S->fn_static, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds));
   }
+  S->Fp = L.padded_features;
+  S->stream_ok = (size_t)S->ns * L.padded_features <= (size_t)kStreamTable;
+  if (S->stream_ok) {
+    S->fn_stream = pick_score2<GroupedStream>(xtype, S->lpr, S->nch > 1, S->ns, S->bin);
+    S->grid_cap_stream = resident_per_cu(S->fn_stream, kThreads, 0) * device_cu_count();
+  }
   S->grid_cap = resident_per_cu(S->fn, kThreads, S->lds) * device_cu_count();
+  S->grid_cap_static = resident_per_cu(S->fn_static, kThreads, S->lds) * device_cu_count();
   for (int64_t b : S->blocks) S->total_blocks += b;
   return NB_OK;
 }
@@ -248,23 +467,50 @@ std::vector<GroupItem> make_items(const GroupSetup& S, int tile_blocks) {
   return items;
 }
 
-// A schedule is a tile size in blocks: 0 = static ranges, > 0 = dynamic
-// items of at most that many blocks.  Its device image (the work list):
+// A schedule code: 0 = static ranges, T > 0 = dynamic items of at most T
+// blocks, -T < 0 = stream items of T blocks.  Its device image (the work
+// list):
 //   [256-byte header: two zeroed int32 counters]
 //   [descriptors, one per group]
-//   [payload: items (dynamic) or the first block of each group plus the
-//    total (static: n_groups + 1 int64)]
+//   [payload: static: the first block of each group plus the total
+//    (n_groups + 1 int64); dynamic: items; stream: items, then tails]
 struct WorkList {
-  int tile_blocks = 0;
+  int code = 0;
   std::vector<GroupItem> items;
+  std::vector<GroupItem> tails;
   std::vector<int64_t> gstart;
+  bool is_static() const { return code == 0; }
+  bool is_stream() const { return code < 0; }
   int32_t n_items() const { return (int32_t)items.size(); }
+  int32_t n_tails() const { return (int32_t)tails.size(); }
 };
 
-WorkList make_work_list(const GroupSetup& S, int tile_blocks) {
+// Stream items: each group's fast blocks cut into items of T blocks in
+// memory order (a remainder below four blocks joins the item before it);
+// groups with fewer than four fast blocks, and every group's blocks past
+// its fast ones, become tails.
+void make_stream_items(const GroupSetup& S, int T, WorkList* w) {
+  for (size_t g = 0; g < S.blocks.size(); ++g) {
+    const int64_t nb = S.blocks[g];
+    if (nb == 0) continue;
+    const int64_t nf = std::min<int64_t>(nb, S.descs[g].nfast);
+    int64_t b0 = 0;
+    if (nf >= kWaves) {
+      while (b0 < nf) {
+        int64_t len = std::min<int64_t>(T, nf - b0);
+        if (nf - (b0 + len) < kWaves) len = nf - b0;       // fold a short remainder in
+        w->items.push_back(GroupItem{b0, (int32_t)g, (int32_t)len});
+        b0 += len;
+      }
+    }
+    if (b0 < nb) w->tails.push_back(GroupItem{b0, (int32_t)g, (int32_t)(nb - b0)});
+  }
+}
+
+WorkList make_work_list(const GroupSetup& S, int code) {
   WorkList w;
-  w.tile_blocks = tile_blocks;
-  if (tile_blocks == 0) {
+  w.code = code;
+  if (code == 0) {
     w.gstart.resize(S.blocks.size() + 1);
     int64_t acc = 0;
     for (size_t g = 0; g < S.blocks.size(); ++g) {
@@ -272,14 +518,17 @@ WorkList make_work_list(const GroupSetup& S, int tile_blocks) {
       acc += S.blocks[g];
     }
     w.gstart[S.blocks.size()] = acc;
+  } else if (code > 0) {
+    w.items = make_items(S, code);
   } else {
-    w.items = make_items(S, tile_blocks);
+    make_stream_items(S, -code, &w);
   }
   return w;
 }
 
 size_t payload_bytes(const WorkList& w) {
-  return w.tile_blocks == 0 ? w.gstart.size() * sizeof(int64_t) : w.items.size() * sizeof(GroupItem);
+  if (w.is_static()) return w.gstart.size() * sizeof(int64_t);
+  return (w.items.size() + w.tails.size()) * sizeof(GroupItem);
 }
 
 size_t work_list_bytes(size_t n_groups, size_t payload) {
@@ -307,57 +556,87 @@ void serialise(const GroupSetup& S, const WorkList& w, std::vector<uint8_t>* blo
   blob->assign(work_list_bytes(ng, payload_bytes(w)), 0);
   std::memcpy(blob->data() + kCounterBytes, S.descs.data(), ng * sizeof(Score2Args));
   uint8_t* pay = blob->data() + kCounterBytes + align_up(ng * sizeof(Score2Args), kAlign);
-  if (w.tile_blocks == 0) std::memcpy(pay, w.gstart.data(), payload_bytes(w));
-  else std::memcpy(pay, w.items.data(), payload_bytes(w));
+  if (w.is_static()) {
+    std::memcpy(pay, w.gstart.data(), w.gstart.size() * sizeof(int64_t));
+  } else {
+    std::memcpy(pay, w.items.data(), w.items.size() * sizeof(GroupItem));
+    std::memcpy(pay + w.items.size() * sizeof(GroupItem), w.tails.data(), w.tails.size() * sizeof(GroupItem));
+  }
 }
 
-// Launch geometry of a schedule: the kernel and the number of workgroups.
-struct Geometry {
+// Launch of one work list: kernel, grid and the arguments it needs.
+struct LaunchDesc {
   const void* fn = nullptr;
+  size_t lds = 0;
   int grid = 0;
+  int kind = 0;                // 0 static, 1 dynamic, 2 stream
+  int32_t n_items = 0, n_tails = 0, n_groups = 0, Fp = 0, nch = 0;
+  int64_t total_blocks = 0;
 };
 
-Geometry geometry(const GroupSetup& S, const WorkList& w) {
-  Geometry G;
-  if (w.tile_blocks == 0) {
-    G.fn = S.fn_static;
+LaunchDesc describe(const GroupSetup& S, const WorkList& w) {
+  LaunchDesc L;
+  L.n_items = w.n_items();
+  L.n_tails = w.n_tails();
+  L.n_groups = (int32_t)S.descs.size();
+  L.Fp = S.Fp;
+  L.nch = S.nch;
+  L.total_blocks = S.total_blocks;
+  if (w.is_static()) {
+    L.kind = 0;
+    L.fn = S.fn_static;
+    L.lds = S.lds;
     // every workgroup gets at least a few blocks per wave
     const int64_t most = std::max<int64_t>(1, S.total_blocks / (2 * kWaves));
-    G.grid = (int)std::max<int64_t>(1, std::min<int64_t>(S.grid_cap, most));
+    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(S.grid_cap_static, most));
+  } else if (w.code > 0) {
+    L.kind = 1;
+    L.fn = S.fn;
+    L.lds = S.lds;
+    L.grid = std::max(1, std::min(S.grid_cap, L.n_items));
   } else {
-    G.fn = S.fn;
-    G.grid = std::max(1, std::min(S.grid_cap, w.n_items()));
+    L.kind = 2;
+    L.fn = S.fn_stream;
+    L.lds = 0;
+    L.grid = std::max(1, std::min(S.grid_cap_stream, std::max(L.n_items, L.n_tails)));
   }
-  return G;
+  return L;
 }
 
-int launch_grouped(const void* fn, size_t lds, int grid, const DevLists& d, int32_t n_groups, int32_t n_items,
-                   int64_t total_blocks, bool is_static, hipStream_t s) {
-  if (total_blocks == 0) return NB_OK;
-  GroupsArgs g;
+int launch_grouped(const LaunchDesc& L, const DevLists& d, hipStream_t s) {
+  if (L.total_blocks == 0) return NB_OK;
+  GroupsArgs g{};
   g.descs = d.descs;
-  g.items = is_static ? nullptr : static_cast<const GroupItem*>(d.payload);
-  g.gstart = is_static ? static_cast<const int64_t*>(d.payload) : nullptr;
   g.counter = d.counter;
-  g.n_items = n_items;
-  g.n_groups = n_groups;
-  g.total_blocks = total_blocks;
+  g.n_groups = L.n_groups;
+  g.Fp = L.Fp;
+  g.nch = L.nch;
+  g.total_blocks = L.total_blocks;
+  if (L.kind == 0) {
+    g.gstart = static_cast<const int64_t*>(d.payload);
+  } else {
+    g.items = static_cast<const GroupItem*>(d.payload);
+    g.n_items = L.n_items;
+    g.tails = g.items + L.n_items;
+    g.n_tails = L.n_tails;
+  }
   void* args[] = {&g};
-  NB_HIP_CHECK(hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s));
+  NB_HIP_CHECK(hipLaunchKernel(L.fn, dim3(L.grid), dim3(kThreads), args, L.lds, s));
   NB_HIP_CHECK(hipGetLastError());
   return NB_OK;
 }
 
 int launch_grouped(const GroupSetup& S, const WorkList& w, const DevLists& d, hipStream_t s) {
-  const Geometry G = geometry(S, w);
-  return launch_grouped(G.fn, S.lds, G.grid, d, (int32_t)S.descs.size(), w.n_items(), S.total_blocks,
-                        w.tile_blocks == 0, s);
+  return launch_grouped(describe(S, w), d, s);
 }
 
+// Default schedule: the stream when the table fits, else static ranges.
+int default_code(const GroupSetup& S) { return S.stream_ok ? -16 : 0; }
+
 // ------------------------------------------------------------ tile cache
-// Tuned schedules persist in a flat JSON object {"key": tile_blocks, ...}
-// (0 = static ranges) at the path named by NB_TUNE_CACHE (when set); always
-// kept in memory.
+// Tuned schedules persist in a flat JSON object {"key": code, ...} (the
+// schedule code above) at the path named by NB_TUNE_CACHE (when set);
+// always kept in memory.
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
@@ -386,8 +665,7 @@ void tune_load_locked() {
     const std::string key = t.substr(i + 1, j - i - 1);
     size_t k = t.find(':', j);
     if (k == std::string::npos) break;
-    const int v = std::atoi(t.c_str() + k + 1);
-    if (v >= 0) g_tune[key] = v;
+    g_tune[key] = std::atoi(t.c_str() + k + 1);
     i = t.find_first_of(",}", k);
     if (i == std::string::npos) break;
   }
@@ -407,12 +685,14 @@ void tune_store_locked() {
   f << "\n}\n";
 }
 
-// tile in blocks (0 = static ranges), or -1 when the shape was never tuned
-int tune_lookup(const std::string& key) {
+// schedule code recorded for the shape, if any
+bool tune_lookup(const std::string& key, int* code) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
   auto it = g_tune.find(key);
-  return it == g_tune.end() ? -1 : it->second;
+  if (it == g_tune.end()) return false;
+  *code = it->second;
+  return true;
 }
 
 void tune_record(const std::string& key, int tile_blocks) {
@@ -431,23 +711,36 @@ int prepare_group_launch(const nb_model* models, int32_t n_models, const nb_grou
   int rc = setup_groups(models, n_models, groups, n_groups, xtype, wtype, &S);
   if (rc) return rc;
   if (tile_rows < 0) return fail(NB_EINVAL, "tile_rows must be >= 0");
-  const WorkList w = make_work_list(S, tile_rows > 0 ? tile_blocks_from_rows(S, tile_rows) : 0);
+  const WorkList w = make_work_list(S, tile_rows > 0 ? tile_blocks_from_rows(S, tile_rows) : default_code(S));
   serialise(S, w, blob);
-  const Geometry G = geometry(S, w);
-  out->fn = G.fn;
-  out->lds = S.lds;
-  out->grid = G.grid;
-  out->n_items = w.n_items();
-  out->n_groups = n_groups;
-  out->is_static = w.tile_blocks == 0;
-  out->total_blocks = S.total_blocks;
+  const LaunchDesc L = describe(S, w);
+  out->fn = L.fn;
+  out->lds = L.lds;
+  out->grid = L.grid;
+  out->kind = L.kind;
+  out->n_items = L.n_items;
+  out->n_tails = L.n_tails;
+  out->n_groups = L.n_groups;
+  out->Fp = L.Fp;
+  out->nch = L.nch;
+  out->total_blocks = L.total_blocks;
   out->blob_bytes = blob->size();
   return NB_OK;
 }
 
-int enqueue_group_launch(const GroupLaunch& L, void* dev_blob, hipStream_t s) {
-  return launch_grouped(L.fn, L.lds, L.grid, carve(dev_blob, L.n_groups), L.n_groups, L.n_items, L.total_blocks,
-                        L.is_static, s);
+int enqueue_group_launch(const GroupLaunch& G, void* dev_blob, hipStream_t s) {
+  LaunchDesc L;
+  L.fn = G.fn;
+  L.lds = G.lds;
+  L.grid = G.grid;
+  L.kind = G.kind;
+  L.n_items = G.n_items;
+  L.n_tails = G.n_tails;
+  L.n_groups = G.n_groups;
+  L.Fp = G.Fp;
+  L.nch = G.nch;
+  L.total_blocks = G.total_blocks;
+  return launch_grouped(L, carve(dev_blob, G.n_groups), s);
 }
 
 }  // namespace nb
@@ -477,19 +770,21 @@ int upload(nb_group_plan* p, const WorkList& w) {
   return NB_OK;
 }
 
-// Time the static schedule and several dynamic tiles on the caller's data;
-// keep the fastest.
+// Time the stream schedule at a few item sizes, static ranges and a few
+// dynamic tiles on the caller's data; keep the fastest.
 int autotune(nb_group_plan* p, hipStream_t s) {
-  std::vector<int> cand = {0};
+  std::vector<int> cand;
+  if (p->S.stream_ok)
+    for (int t : {8, 16, 32, 64}) cand.push_back(-t);
+  cand.push_back(0);
   const int def = default_tile_blocks(p->S);
-  for (int t : {8, 16, 32, 64, 128, def}) cand.push_back(t);
-  std::sort(cand.begin() + 1, cand.end());
-  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  for (int t : {16, 32, 64, 128}) cand.push_back(t);
+  if (std::find(cand.begin(), cand.end(), def) == cand.end()) cand.push_back(def);
   hipEvent_t e0, e1;
   NB_HIP_CHECK(hipEventCreate(&e0));
   NB_HIP_CHECK(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_t = 0;
+  int best_t = default_code(p->S);
   int rc = NB_OK;
   const DevLists d = carve(p->dev, p->n_groups);
   for (int t : cand) {
@@ -515,7 +810,7 @@ int autotune(nb_group_plan* p, hipStream_t s) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
-  p->w.tile_blocks = best_t;
+  p->w.code = best_t;
   p->tuned = 1;
   return NB_OK;
 }
@@ -533,24 +828,31 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
   int rc = setup_groups(models, n_models, groups, n_groups, xtype, wtype, &p->S);
   if (rc) return rc;
   p->n_groups = n_groups;
-  // room for the largest work list any schedule makes (the smallest tile)
-  const WorkList smallest = make_work_list(p->S, kWaves);
-  p->dev_bytes = std::max(work_list_bytes(n_groups, payload_bytes(smallest)),
-                          work_list_bytes(n_groups, (n_groups + 1) * sizeof(int64_t)));
+  // room for the largest work list any schedule makes (the smallest tiles)
+  p->dev_bytes = std::max({work_list_bytes(n_groups, payload_bytes(make_work_list(p->S, kWaves))),
+                           work_list_bytes(n_groups, payload_bytes(make_work_list(p->S, -kWaves))),
+                           work_list_bytes(n_groups, (n_groups + 1) * sizeof(int64_t))});
   NB_HIP_CHECK(hipStreamSynchronize(s));
   NB_HIP_CHECK(hipMalloc(&p->dev, p->dev_bytes));
   const std::string key = tune_key(p->S, n_groups);
   int tile = 0;
-  if (tile_rows > 0) {
+  int cached = 0;
+  if (flags & NB_PLAN_STATIC) {
+    tile = 0;
+  } else if (flags & NB_PLAN_STREAM) {
+    if (!p->S.stream_ok) return fail(NB_EINVAL, "stream schedule: the scoring rows exceed 2048 floats");
+    tile = tile_rows > 0 ? -tile_blocks_from_rows(p->S, tile_rows) : default_code(p->S);
+  } else if (tile_rows > 0) {
     tile = tile_blocks_from_rows(p->S, tile_rows);
-  } else if ((tile = tune_lookup(key)) >= 0) {
+  } else if (tune_lookup(key, &cached)) {
+    tile = cached;
     p->tuned = 2;
   } else if (flags & NB_PLAN_TUNE) {
     if ((rc = autotune(p, s))) return rc;
-    tile = p->w.tile_blocks;
+    tile = p->w.code;
     tune_record(key, tile);
   } else {
-    tile = 0;
+    tile = default_code(p->S);
   }
   if ((rc = upload(p, make_work_list(p->S, tile)))) return rc;
   // capture the launch into a graph on a private stream
@@ -612,7 +914,8 @@ int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_grou
   if (!out) return fail(NB_EINVAL, "out is NULL");
   *out = nullptr;
   if (tile_rows < 0) return fail(NB_EINVAL, "tile_rows must be >= 0");
-  if (flags & ~NB_PLAN_TUNE) return fail(NB_EINVAL, "unknown plan flags");
+  if (flags & ~(NB_PLAN_TUNE | NB_PLAN_STATIC | NB_PLAN_STREAM)) return fail(NB_EINVAL, "unknown plan flags");
+  if ((flags & NB_PLAN_STATIC) && (flags & NB_PLAN_STREAM)) return fail(NB_EINVAL, "pick one schedule");
   nb_group_plan* p = new (std::nothrow) nb_group_plan();
   if (!p) return fail(NB_ENOMEM, "out of host memory");
   const int rc = plan_build(p, models, n_models, groups, n_groups, xtype, wtype, tile_rows, flags,
@@ -636,13 +939,13 @@ int nb_group_plan_launch(nb_group_plan* plan, void* stream) {
 int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out) {
   if (!plan || !out) return fail(NB_EINVAL, "NULL argument");
   const int br = (64 / plan->S.lpr) * kRowSteps;
-  const Geometry G = geometry(plan->S, plan->w);
-  out->schedule = plan->w.tile_blocks == 0 ? NB_SCHEDULE_STATIC : NB_SCHEDULE_DYNAMIC;
-  out->tile_rows = plan->w.tile_blocks == 0
-                       ? (int32_t)std::min<int64_t>(INT32_MAX, (plan->S.total_blocks + G.grid - 1) / G.grid * br)
-                       : plan->w.tile_blocks * br;
-  out->n_items = plan->w.tile_blocks == 0 ? G.grid : plan->w.n_items();
-  out->grid = G.grid;
+  const LaunchDesc L = describe(plan->S, plan->w);
+  const int code = plan->w.code;
+  out->schedule = code == 0 ? NB_SCHEDULE_STATIC : (code > 0 ? NB_SCHEDULE_DYNAMIC : NB_SCHEDULE_STREAM);
+  out->tile_rows = code == 0 ? (int32_t)std::min<int64_t>(INT32_MAX, (plan->S.total_blocks + L.grid - 1) / L.grid * br)
+                             : std::abs(code) * br;
+  out->n_items = code == 0 ? L.grid : L.n_items + L.n_tails;
+  out->grid = L.grid;
   out->tuned = plan->tuned;
   out->n_files = plan->S.n_files;
   out->rows_per_block = br;

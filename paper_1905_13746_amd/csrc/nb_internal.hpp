@@ -78,9 +78,12 @@ struct GroupLaunch {
   const void* fn = nullptr;
   size_t lds = 0;
   int32_t grid = 0;
+  int32_t kind = 0;            // schedule: 0 static ranges, 1 dynamic items, 2 stream
   int32_t n_items = 0;
+  int32_t n_tails = 0;
   int32_t n_groups = 0;
-  bool is_static = true;
+  int32_t Fp = 0;
+  int32_t nch = 0;
   int64_t total_blocks = 0;
   size_t blob_bytes = 0;
 };

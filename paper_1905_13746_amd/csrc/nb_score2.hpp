@@ -286,13 +286,13 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
   dev::u32x4 buf0[R][NV], buf1[R][NV];
   int ib = 0;       // index of the block being issued, among this wave's blocks
   int ich = 0;      // chunk being issued
-  auto rewind = [&]() {          // point the issue cursor back at the last issued unit
-    if (ich == 0) {
-      ich = nch - 1;
-      --ib;
-    } else {
-      --ich;
-    }
+  // point the issue cursor back at the last issued unit; written as value
+  // selects: a branch that decrements one of two counters becomes a store
+  // to a selected address, which moves both counters to scratch memory
+  auto rewind = [&]() {
+    const bool wrap = ich == 0;
+    ib = wrap ? ib - 1 : ib;
+    ich = wrap ? nch - 1 : ich - 1;
   };
   auto issue = [&](dev::u32x4 (&dst)[R][NV]) {
     const int64_t blk = first + (int64_t)ib * stride;

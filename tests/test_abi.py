@@ -194,6 +194,7 @@ def test_group_plan_rejects_before_allocating(lib):
     assert not out.value
     cg = (_lib.NbGroup * 1)(_group(0))
     assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, -5, 0, None, ctypes.byref(out)) == -1
-    assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, 0, 4, None, ctypes.byref(out)) == -1
+    assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, 0, 8, None, ctypes.byref(out)) == -1    # unknown flag
+    assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, 0, 2 | 4, None, ctypes.byref(out)) == -1  # two schedules
     assert lib.nb_group_plan_destroy(None) == 0
     assert lib.nb_group_plan_launch(None, None) == -1

@@ -114,7 +114,7 @@ def test_groups_other_shapes(F, xdtype, fp8):
 def test_tile_invariance():
     _case("groups tile invariance")
     models, _, gmodel, xs, _, _ = _build(2000, nb.MULTINOMIAL)
-    ref = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True)      # static ranges
+    ref = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True)      # default schedule
     for tile in (1, 8, 40, 1000, 1 << 20):                                  # dynamic items
         got = nbg.score_groups(models, list(zip(gmodel, xs)), scores=True, tile_rows=tile)
         torch.cuda.synchronize()
@@ -129,7 +129,7 @@ def test_plan_graph_replays_equal_eager():
     plan = nbg.GroupPlan(models, list(zip(gmodel, xs)), scores=True)
     info = plan.info()
     assert info["n_files"] == sum(SIZES) and info["n_items"] > 0 and info["grid"] >= 1
-    assert info["schedule"] == "static"
+    assert info["schedule"] in ("stream", "static")
     for rep in range(4):
         for o in plan.outs:
             for t in o:
@@ -150,7 +150,7 @@ def test_plan_new_data_in_same_buffers(tile):
     _case(f"groups plan refill tile={tile}")
     models, oms, gmodel, xs, _, route = _build(1000, nb.MULTINOMIAL)
     plan = nbg.GroupPlan(models, list(zip(gmodel, xs)), tile_rows=tile)
-    assert plan.info()["schedule"] == ("static" if tile == 0 else "dynamic")
+    assert plan.info()["schedule"] == ("stream" if tile == 0 else "dynamic")
     for step in range(2):
         for g, x in enumerate(xs):
             if x.shape[0]:
@@ -162,6 +162,25 @@ def test_plan_new_data_in_same_buffers(tile):
             if SIZES[g]:
                 _assert_equal(plan.outs[g], _alone(models, gmodel, route, xs, g, nbg.W_F32, False, False))
     plan.close()
+
+
+@pytest.mark.parametrize("F,scores", [(2000, False), (1000, True), (100, True), (500, False)])
+def test_every_schedule_matches_alone(F, scores):
+    """Each schedule a plan can pick (stream at several item sizes, static
+    ranges, dynamic items) gives each group nb_score's own results."""
+    _case(f"groups schedules F={F} scores={scores}")
+    models, _, gmodel, xs, _, route = _build(F, nb.MULTINOMIAL)
+    groups = list(zip(gmodel, xs))
+    for sched, tile in (("stream", 1), ("stream", 100), ("stream", 5000), ("stream", 0), ("static", 0),
+                        (None, 64), (None, 2048)):
+        plan = nbg.GroupPlan(models, groups, scores=scores, schedule=sched, tile_rows=tile)
+        assert plan.info()["schedule"] == (sched or "dynamic")
+        plan.launch()
+        torch.cuda.synchronize()
+        for g in range(len(SIZES)):
+            if SIZES[g]:
+                _assert_equal(plan.outs[g], _alone(models, gmodel, route, xs, g, nbg.W_F32, False, scores))
+        plan.close()
 
 
 def test_plan_autotune_and_cache(tmp_path):

@@ -9,8 +9,9 @@
 // followed by C*F logarithms.  The reductions are HBM-bound (one pass over
 // the training matrix); the logarithms are negligible.
 //
-// Kernel pipeline (one stream):
-//   init_status   zero the model's status word
+// Kernel pipeline (one stream).  Error flags travel as plain per-workgroup
+// words in the workspace and are OR-ed down the pipeline; form_rows writes
+// the model's status word once, so no kernel has to clear it first.
 //   count_kernel  grid (slot, class, chunk): each workgroup streams the rows
 //                 of ONE class inside its slot of rows and ONE 1024-feature
 //                 chunk.  Labels are read 64 at a time and compacted with a
@@ -41,8 +42,10 @@ constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kSeg = 16;                  // features per lane per chunk
 constexpr int kChunk = 64 * kSeg;         // features per chunk (one wave)
-constexpr int kBatch = 8;                 // rows loaded together by a wave
-constexpr int kTargetUnits = 1024;        // (slot, class, chunk) workgroups aimed at
+// rows loaded together by a wave: sixteen 16-byte loads in flight for byte
+// features, eight rows of four loads for int32 features
+template <int XT>
+constexpr int batch_rows() { return XT == NB_X_I32 ? 8 : 16; }
 constexpr int64_t kMinRowsPerSlot = 512;
 
 struct CountArgs {
@@ -54,20 +57,19 @@ struct CountArgs {
   int64_t rows_per_slot;
   int64_t* part;           // [S][C][Fp]
   int64_t* nc_part;        // [S][C]
-  int32_t* status;
+  int32_t* flag_part;      // [S][C][chunks] error flags of each workgroup
   int32_t F, C, Fp;
 };
-
-__global__ void init_status(int32_t* status) {
-  if (threadIdx.x < 4) status[threadIdx.x] = 0;
-}
 
 template <int XT, bool BIN>
 __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;   // bytes per feature
   constexpr int NV = EB;                          // 16-byte vectors per lane per row
+  constexpr int kBatch = batch_rows<XT>();
   const int slot = blockIdx.x, cls = blockIdx.y, ch = blockIdx.z;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave-uniform (readfirstlane): row ranges and buffer descriptors derived
+  // from it then live in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   const int64_t r_begin = (int64_t)slot * a.rows_per_slot;
   const int64_t r_end = min(a.n, r_begin + a.rows_per_slot);
@@ -105,6 +107,10 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   for (int64_t base = w_begin; base < w_end; base += 64) {
     const int64_t r = base + lane;
     const int lab = (r < w_end) ? a.y[r] : -1;
+    // the whole 64-row window (its chunk) lies inside the buffer
+    const bool window_fast =
+        (base + 63) * a.ld_bytes + chunk_end <= a.total_bytes && 64 * a.ld_bytes < ((int64_t)1 << 31);
+    const auto wrsrc = dev::make_rsrc(a.x + base * a.ld_bytes, a.total_bytes - base * a.ld_bytes);
     if (r < w_end && (lab < 0 || lab >= a.C)) bad_label = true;
     uint64_t mask = __ballot(lab == cls);
     matched += __popcll(mask);
@@ -123,6 +129,22 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
         }
       }
       dev::u32x4 v[kBatch][NV];
+      if (window_fast) {
+        // every row of the window is in bounds: one descriptor for the
+        // window, all loads issued unconditionally (slots past cnt re-read
+        // the batch's first row and are zeroed afterwards)
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+          const uint32_t ro = (uint32_t)((k < cnt ? rows[k] : rows[0]) - base) * (uint32_t)a.ld_bytes;
+#pragma unroll
+          for (int q = 0; q < NV; ++q) v[k][q] = dev::buffer_load16(wrsrc, ro + (uint32_t)col + 16 * q);
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k)
+#pragma unroll
+          for (int q = 0; q < NV; ++q)
+            if (k >= cnt) v[k][q] = dev::u32x4{0u, 0u, 0u, 0u};
+      } else {
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
 #pragma unroll
@@ -141,6 +163,7 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
               v[k][q] = dev::load16_guarded(p + 16 * q, a.total_bytes - (row_off + col + 16 * q));
           }
         }
+      }
       }
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
@@ -178,8 +201,13 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   }
   if (XT != NB_X_I32) flush();
 
-  if (bad_label && cls == 0 && ch == 0) atomicOr(&a.status[kStatusFlags], kFlagBadLabel);
-  if (negative) atomicOr(&a.status[kStatusFlags], kFlagNegative);
+  {
+    const int any_bad = __syncthreads_or(bad_label && cls == 0 && ch == 0);
+    const int any_neg = __syncthreads_or(negative);
+    if (threadIdx.x == 0)
+      a.flag_part[((int64_t)slot * a.C + cls) * gridDim.z + ch] =
+          (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0);
+  }
 
   // combine the four waves in LDS, then one partial row per workgroup
   __shared__ int64_t red[kWaves - 1][kSeg][64];
@@ -218,11 +246,23 @@ __global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__
   const int stride = 4 * RS;
   if (f < F) {
     int k = rs * 4 + sg;
-#pragma unroll 4
-    for (; k < S; k += stride) s += part[((int64_t)k * C + c) * Fp + f];
+    // sixteen partials in flight per lane, then their sum
+    for (; k < S; k += 16 * stride) {
+      int64_t v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int kk = k + u * stride;
+        v[u] = (kk < S) ? part[((int64_t)kk * C + c) * Fp + f] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
   }
-  if (blockIdx.x == 0 && fl == 0)
-    for (int k = rs * 4 + sg; k < S; k += stride) m += nc_part[(int64_t)k * C + c];
+  if (blockIdx.x == 0) {     // class totals: spread over the 64 lanes, then a wave sum
+    for (int k = rs * 4 + sg + fl * stride; k < S; k += 64 * stride) m += nc_part[(int64_t)k * C + c];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m += __shfl_xor(m, o);
+  }
   __shared__ int64_t red[4][64];
   __shared__ int64_t redm[4];
   red[sg][fl] = s;
@@ -244,52 +284,87 @@ struct TableArgs {
   double* log_1m_theta;
   double* weight;
   double* bias;
-  int32_t* status;
+  const int32_t* flag_part;  // [n_flags] the count kernel's per-workgroup flags
+  int32_t* class_flags;      // [C] error flags gathered by each class's workgroup
   double alpha;
-  int32_t F, C, Fp, RS, kind, min_files;
+  int32_t F, C, Fp, RS, kind, min_files, n_flags;
 };
+
+// Sum over the 256 threads of a workgroup: wave shuffles, then the four
+// wave totals in a fixed order (deterministic for floating point).
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T* red4) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red4[0] + red4[1] + red4[2] + red4[3];
+}
 
 // One workgroup per class: finish the counts (sum of the second-level
 // partials, int32 range check), S_c, N_c, then the FP64 tables.
 __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
   const int c = blockIdx.x;
   const int t = threadIdx.x;
-  __shared__ int64_t si[256];
-  __shared__ double sd[256];
   int32_t* T = a.counts + (int64_t)c * a.F;
 
+  // Every partial is loaded before any is summed (the loads are independent;
+  // summed one at a time they would form a chain of L2 round trips).
+  constexpr int kFeatPerPass = 4;
   int64_t s = 0;
   bool over = false;
-  for (int f = t; f < a.F; f += 256) {
-    int64_t v = 0;
-    for (int r = 0; r < a.RS; ++r) v += a.part2[((int64_t)r * a.C + c) * a.Fp + f];
-    if (v > INT32_MAX) {
-      over = true;
-      v = INT32_MAX;
+  for (int f0 = t; f0 < a.F; f0 += 256 * kFeatPerPass) {
+    int64_t v[kFeatPerPass][kReduceSplit];
+#pragma unroll
+    for (int q = 0; q < kFeatPerPass; ++q) {
+      const int f = f0 + q * 256;
+#pragma unroll
+      for (int r = 0; r < kReduceSplit; ++r)
+        v[q][r] = (f < a.F && r < a.RS) ? a.part2[((int64_t)r * a.C + c) * a.Fp + f] : 0;
     }
-    T[f] = (int32_t)v;
-    s += v;
+#pragma unroll
+    for (int q = 0; q < kFeatPerPass; ++q) {
+      const int f = f0 + q * 256;
+      int64_t tot = 0;
+#pragma unroll
+      for (int r = 0; r < kReduceSplit; ++r) tot += v[q][r];
+      if (f < a.F) {
+        if (tot > INT32_MAX) {
+          over = true;
+          tot = INT32_MAX;
+        }
+        T[f] = (int32_t)tot;
+        s += tot;
+      }
+    }
   }
-  if (over) atomicOr(&a.status[kStatusFlags], kFlagOverflow);
-  si[t] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) si[t] += si[t + w];
-    __syncthreads();
+  // the count kernel's flags (every class workgroup gathers all of them)
+  int32_t fl = 0;
+  for (int i = t; i < a.n_flags; i += 256) fl |= a.flag_part[i];
+  const int any_over = __syncthreads_or(over);
+  const int any_bad = __syncthreads_or(fl & kFlagBadLabel);
+  const int any_neg = __syncthreads_or(fl & kFlagNegative);
+  // class totals: one partial per thread, summed in a fixed order
+  __shared__ int64_t snc[kMaxClasses];
+  if (t < a.C) {
+    int64_t w[kReduceSplit];
+#pragma unroll
+    for (int r = 0; r < kReduceSplit; ++r) w[r] = (r < a.RS) ? a.nc2[(int64_t)r * a.C + t] : 0;
+    int64_t tot = 0;
+#pragma unroll
+    for (int r = 0; r < kReduceSplit; ++r) tot += w[r];
+    snc[t] = tot;
   }
-  const int64_t Sc = si[0];
-  // N_c of every class (each block needs N = sum_c N_c)
-  int64_t N = 0, Nc = 0;
-  for (int k = 0; k < a.C; ++k) {
-    int64_t v = 0;
-    for (int r = 0; r < a.RS; ++r) v += a.nc2[(int64_t)r * a.C + k];
-    N += v;
-    if (k == c) Nc = v;
-  }
+  __shared__ int64_t red_i[4];
+  const int64_t Sc = block_sum<int64_t>(s, red_i);
+  int64_t N = 0;
+  for (int k = 0; k < a.C; ++k) N += snc[k];
+  const int64_t Nc = snc[c];
   if (t == 0) {
     a.class_totals[c] = Nc;
     a.class_sums[c] = (a.kind == NB_MULTINOMIAL) ? Sc : Nc;
-    if (Nc < a.min_files || Nc < 1) atomicOr(&a.status[kStatusFlags], kFlagMinFiles);
+    a.class_flags[c] = (any_over ? kFlagOverflow : 0) | ((Nc < a.min_files || Nc < 1) ? kFlagMinFiles : 0) |
+                       (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0);
   }
 
   const double al = a.alpha;
@@ -315,21 +390,18 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
       part += l1;
     }
   }
-  sd[t] = part;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) sd[t] += sd[t + w];
-    __syncthreads();
-  }
+  __shared__ double red_d[4];
+  const double sum_l1 = block_sum<double>(part, red_d);
   if (t == 0) {
     const double lp = log((double)Nc) - log((double)N);
-    a.bias[c] = (a.kind == NB_MULTINOMIAL) ? lp : lp + sd[0];
+    a.bias[c] = (a.kind == NB_MULTINOMIAL) ? lp : lp + sum_l1;
   }
 }
 
 __global__ __launch_bounds__(256) void form_rows(const double* __restrict__ W, const double* __restrict__ bias,
                                                 int C, int F, int Fp, float* __restrict__ rows32,
                                                 uint16_t* __restrict__ rows16, float* __restrict__ row_bias,
+                                                const int32_t* __restrict__ class_flags,
                                                 int32_t* __restrict__ status) {
   const int f = blockIdx.x * 256 + threadIdx.x;
   const int P = (C == 2) ? 1 : C;
@@ -370,13 +442,29 @@ __global__ __launch_bounds__(256) void form_rows(const double* __restrict__ W, c
       for (int c = 0; c < C; ++c) row_bias[c] = (float)(bias[c] - mb);
       row_bias[C] = (float)mb;
     }
-    status[kStatusTrained] = (status[kStatusFlags] == 0) ? 1 : 0;
+    int32_t flags = 0;
+    for (int c = 0; c < C; ++c) flags |= class_flags[c];
+    status[kStatusFlags] = flags;
+    status[kStatusTrained] = (flags == 0) ? 1 : 0;
+    status[2] = 0;
+    status[3] = 0;
   }
 }
 
-int64_t train_slots(int32_t C, int32_t F, int64_t n) {
+// Workgroups of the count kernel resident on the device at once.
+int count_capacity(int32_t xtype) {
+  const void* fn = (xtype == NB_X_I32) ? reinterpret_cast<const void*>(count_kernel<NB_X_I32, false>)
+                                       : reinterpret_cast<const void*>(count_kernel<NB_X_U8, false>);
+  return resident_per_cu(fn, kThreads, 0) * device_cu_count();
+}
+
+// Row slots of the count pass: as many (slot, class, chunk) workgroups as
+// fit on the device in one round (a few more would run as a second, nearly
+// empty round), with at least kMinRowsPerSlot rows per slot.
+int64_t train_slots(int32_t C, int32_t F, int64_t n, int32_t xtype) {
   const int64_t nch = (align_up((size_t)F, kFeaturePad)) / kChunk;
-  int64_t s = (kTargetUnits + C * nch - 1) / (C * nch);
+  const int64_t units = std::max<int64_t>(1, count_capacity(xtype));
+  const int64_t s = std::max<int64_t>(1, units / (C * nch));
   const int64_t by_rows = std::max<int64_t>(1, (n + kMinRowsPerSlot - 1) / kMinRowsPerSlot);
   return std::max<int64_t>(1, std::min(s, by_rows));
 }
@@ -385,7 +473,7 @@ int64_t train_slots(int32_t C, int32_t F, int64_t n) {
 // second-level partials of each.
 struct TrainWs {
   int64_t S, RS;
-  size_t off_part, off_nc, off_part2, off_nc2, total;
+  size_t off_part, off_nc, off_part2, off_nc2, off_flags, total;
 };
 
 TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
@@ -402,6 +490,8 @@ TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
   w.off_nc = take((size_t)S * C * 8);
   w.off_part2 = take((size_t)w.RS * C * Fp * 8);
   w.off_nc2 = take((size_t)w.RS * C * 8);
+  // count-kernel flags [S][C][chunks], then per-class flags
+  w.off_flags = take(((size_t)S * C * (Fp / kChunk) + C) * 4);
   w.total = off;
   return w;
 }
@@ -424,7 +514,7 @@ extern "C" {
 size_t nb_train_workspace_bytes(int32_t n_classes, int32_t n_features, int64_t n, int32_t xtype) {
   nb_layout L;
   if (!compute_layout(n_classes, n_features, &L) || n < 0 || elem_bytes(xtype) == 0) return 0;
-  return train_ws(n_classes, L.padded_features, train_slots(n_classes, n_features, n)).total;
+  return train_ws(n_classes, L.padded_features, train_slots(n_classes, n_features, n, xtype)).total;
 }
 
 int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, const int32_t* y,
@@ -456,16 +546,16 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   uint8_t* base = static_cast<uint8_t*>(m->dev);
   int32_t* status = reinterpret_cast<int32_t*>(base + L.off_status);
   const int Fp = L.padded_features;
-  const int64_t S = train_slots(C, F, n);
+  const int64_t S = train_slots(C, F, n, xtype);
   const TrainWs tw = train_ws(C, Fp, S);
   uint8_t* wsb = static_cast<uint8_t*>(workspace);
   int64_t* part = reinterpret_cast<int64_t*>(wsb + tw.off_part);
   int64_t* nc_part = reinterpret_cast<int64_t*>(wsb + tw.off_nc);
   int64_t* part2 = reinterpret_cast<int64_t*>(wsb + tw.off_part2);
   int64_t* nc2 = reinterpret_cast<int64_t*>(wsb + tw.off_nc2);
-
-  hipLaunchKernelGGL(init_status, dim3(1), dim3(64), 0, s, status);
-  NB_HIP_CHECK(hipGetLastError());
+  const int n_flags = (int)(S * C * (Fp / kChunk));
+  int32_t* flag_part = reinterpret_cast<int32_t*>(wsb + tw.off_flags);
+  int32_t* class_flags = flag_part + n_flags;
 
   CountArgs ca;
   ca.x = static_cast<const uint8_t*>(x);
@@ -476,7 +566,7 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   ca.rows_per_slot = (n + S - 1) / S;
   ca.part = part;
   ca.nc_part = nc_part;
-  ca.status = status;
+  ca.flag_part = flag_part;
   ca.F = F;
   ca.C = C;
   ca.Fp = Fp;
@@ -505,7 +595,9 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   ta.log_1m_theta = reinterpret_cast<double*>(base + L.off_log_1m_theta);
   ta.weight = reinterpret_cast<double*>(base + L.off_weight);
   ta.bias = reinterpret_cast<double*>(base + L.off_bias);
-  ta.status = status;
+  ta.flag_part = flag_part;
+  ta.class_flags = class_flags;
+  ta.n_flags = n_flags;
   ta.alpha = alpha;
   ta.F = F;
   ta.C = C;
@@ -519,7 +611,7 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   hipLaunchKernelGGL(form_rows, dim3((unsigned)(Fp / 256)), dim3(256), 0, s, ta.weight, ta.bias, C, F, Fp,
                      reinterpret_cast<float*>(base + L.off_form_f32),
                      reinterpret_cast<uint16_t*>(base + L.off_form_bf16),
-                     reinterpret_cast<float*>(base + L.off_form_bias), status);
+                     reinterpret_cast<float*>(base + L.off_form_bias), class_flags, status);
   NB_HIP_CHECK(hipGetLastError());
 
   if (flags & NB_TRAIN_ASYNC) return NB_OK;

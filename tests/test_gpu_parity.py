@@ -192,6 +192,17 @@ def test_training_errors_detected_on_device():
     # asynchronous training reports through nb_model_status
     nbg.train(m, X, bad, asynchronous=True)
     assert nbg.model_status(m) == -5
+    # a count above INT32_MAX (int32 features), then a clean run clears the flags
+    Xo = Xi.clone()
+    Xo[Xo < 0] = 0
+    Xo[0, 3] = 1 << 30
+    Xo[2, 3] = 1 << 30                     # rows 0 and 2 share class 0
+    with pytest.raises(nbg.NBError) as e:
+        nbg.train(mi, Xo, yi)
+    assert e.value.code == -2 and not mi.trained
+    Xo[2, 3] = 7
+    nbg.train(mi, Xo, yi)
+    assert mi.trained and nbg.model_status(mi) == 0
 
 
 @pytest.mark.slow

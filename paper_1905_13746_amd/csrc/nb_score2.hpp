@@ -28,6 +28,8 @@ constexpr int kThreads = 64 * kWaves;
 #define NB_PIPELINE 1
 #endif
 constexpr int kRowSteps = NB_ROW_STEPS;
+// the transposed butterfly of finish_block halves R x NS values per step
+static_assert((kRowSteps & (kRowSteps - 1)) == 0, "row steps per block must be a power of two");
 constexpr bool kPipeline = NB_PIPELINE != 0;
 
 struct Score2Args {

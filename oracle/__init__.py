@@ -13,6 +13,10 @@ Modules
              and the malware/benign decision that follows it)
   groups     size-group model validity and fallback routing (section 4, the
              fewer-than-six-files rule and the next-group fallback)
+  select     per-group top-k feature selection by the normalised malware-benign
+             occurrence difference, the feature gather, and the model trained
+             on the selected features (section 3 feature selection; section 4,
+             each group trained and tested on its top-k features)
   precision  reduced-precision mirrors: BF16 and FP32 round-to-nearest-even
              from FP64, FP8-e4m3 quantisation of counts, certified label bands
 
@@ -21,4 +25,4 @@ example, exact rationals, library cross-checks, invariants); none is
 "parity unpinned".  The paper's own empirical results (about 87% accuracy,
 up to 200x speed-up) need its dataset and hardware and are not reproduced.
 """
-from . import nb, groups, precision  # noqa: F401
+from . import nb, groups, precision, select  # noqa: F401

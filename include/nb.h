@@ -39,7 +39,8 @@ extern "C" {
 #define NB_EOVERFLOW  -2  /* a count would not fit its exact integer type      */
 #define NB_EMINFILES  -3  /* a class has fewer training files than required    */
 #define NB_ENOMODEL   -4  /* no group has a trained model to fall back on      */
-#define NB_EDATA      -5  /* label outside [0, C) or negative feature value     */
+#define NB_EDATA      -5  /* label outside [0, C), negative feature value, or
+                             feature index outside [0, F)                      */
 #define NB_ENOMEM     -6  /* workspace or arena too small                       */
 #define NB_EHIP       -7  /* a HIP runtime call failed                           */
 #define NB_EREJECTED  -8  /* serving: request can never fit the arena           */
@@ -153,6 +154,57 @@ int nb_score(const nb_model* model, const void* x, int32_t xtype, int64_t n, int
  * x: uint8 [n x F] (stride ld_x), out: uint8 [n x F] (stride ld_out). */
 int nb_quantize_fp8(const uint8_t* x, int64_t n, int32_t n_features, int64_t ld_x,
                     uint8_t* out, int64_t ld_out, void* stream);
+
+/* ------------------------------------------------------ feature selection
+ * Section 3: each size group keeps the k opcodes that best separate its
+ * malware from its benign files, ranked by the difference of the two
+ * classes' normalised occurrences; section 4 trains and classifies each
+ * group on those k features.  The normalisation is only cited by the paper;
+ * the library's reading, for a trained two-class model with counts T and
+ * class sums S (nb_layout: off_counts, off_class_sums, i.e. occurrences and
+ * their class total for multinomial models, presence counts and N_c for
+ * Bernoulli ones):
+ *     d_f = | T_1f / S_1 - T_0f / S_0 |
+ * The ranking is exact: d_f S_0 S_1 = |T_1f S_0 - T_0f S_1| is compared as
+ * a 128-bit integer (when one class has S_c = 0, d_f is the other class's
+ * share, ranked by its T_f).  An exact tie goes to the lower feature index.
+ *
+ * models: n_models trained two-class models (trained != 0), any kinds and
+ * feature counts, 1 <= k <= F of every model.
+ * idx: device int32 [n_models x ld_idx], ld_idx >= k: row m receives the k
+ * selected feature indices of models[m] in ascending order.
+ * Enqueues on `stream` and returns.  Errors: NB_EINVAL. */
+int nb_select_features(const nb_model* models, int32_t n_models, int32_t k, int32_t* idx, int64_t ld_idx,
+                       void* stream);
+
+/* The model trained on a subset of features, built from a trained model's
+ * counts without re-reading its training files: out's counts are the
+ * columns idx[0..k) of full's counts (column sums, so equal to counting the
+ * gathered training files), its class totals are full's, and its tables
+ * follow from these counts exactly as in nb_train with smoothing alpha (so
+ * a multinomial S_c is the sum over the k selected columns only).
+ * full: trained.  out: its own buffer of nb_model_bytes(C, k), kind and
+ * n_classes equal to full's, n_features = k.  idx: device int32[k] with
+ * values in [0, F) of full (any order, repeats allowed); an index outside
+ * that range is detected on the device and fails with NB_EDATA.
+ * workspace: device scratch of nb_model_select_workspace_bytes(C, k) bytes,
+ * 8-byte aligned.  Synchronises `stream` and returns the outcome, unless
+ * flags holds NB_TRAIN_ASYNC (then nb_model_status() reports it).
+ * Errors: NB_EINVAL, NB_ENOMEM, NB_EDATA. */
+size_t nb_model_select_workspace_bytes(int32_t n_classes, int32_t k);
+int nb_model_select(const nb_model* full, const int32_t* idx, int32_t k, double alpha, nb_model* out,
+                    void* workspace, size_t workspace_bytes, int32_t flags, void* stream);
+
+/* Gather each file's selected features: out[i][j] = x[i][idx[j]].
+ * x: [n x F] elements of xtype (any of NB_X_*; stride ld >= F), idx: device
+ * int32[k] (any order, repeats allowed), out: [n x k] of the same type
+ * (stride ld_out >= k).  int32 data must be 4-byte aligned.  An index
+ * outside [0, F) writes 0 and, when status is not NULL, sets bit 0 of the
+ * device word *status (the library never clears it).  n == 0 is a no-op.
+ * Errors: NB_EINVAL. */
+int nb_gather_features(const void* x, int32_t xtype, int64_t n, int32_t n_features, int64_t ld,
+                       const int32_t* idx, int32_t k, void* out, int64_t ld_out, int32_t* status,
+                       void* stream);
 
 /* ----------------------------------------------------------- size groups
  * Sections 3-4: group g has a model iff every class has >= min_files

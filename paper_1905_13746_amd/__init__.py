@@ -160,6 +160,57 @@ def quantize_fp8(x: torch.Tensor, out: torch.Tensor | None = None, stream=None):
     return out
 
 
+def select_features(models, k: int, out: torch.Tensor | None = None, stream=None):
+    """Top-k features of each trained two-class model by the normalised
+    class occurrence difference: int32 [len(models), k], rows ascending."""
+    models = list(models)
+    arr = (_lib.NbModel * len(models))(*[m.c for m in models])
+    if out is None:
+        out = torch.empty((len(models), int(k)), dtype=torch.int32, device=models[0].buf.device)
+    if out.dtype != torch.int32 or out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be a row-major int32 [n_models, >= k] tensor")
+    check(load().nb_select_features(arr, len(models), int(k), _ptr(out), out.stride(0), _stream(stream)),
+          "nb_select_features")
+    return out
+
+
+def model_on_features(full: Model, idx: torch.Tensor, alpha: float = 1.0, workspace: torch.Tensor | None = None,
+                      asynchronous: bool = False, stream=None) -> Model:
+    """The model trained on the features idx (int32, device), built from
+    full's counts without its training files."""
+    if idx.dtype != torch.int32 or idx.dim() != 1 or not idx.is_contiguous():
+        raise ValueError("idx must be a contiguous 1-D int32 tensor")
+    k = idx.numel()
+    m = Model(full.n_classes, k, full.kind, device=full.buf.device)
+    if workspace is None:
+        nbytes = load().nb_model_select_workspace_bytes(full.n_classes, k)
+        workspace = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=full.buf.device)
+    rc = load().nb_model_select(ctypes.byref(full.c), _ptr(idx), k, float(alpha), ctypes.byref(m.c),
+                                _ptr(workspace), workspace.numel(), TRAIN_ASYNC if asynchronous else 0,
+                                _stream(stream))
+    check(rc, "nb_model_select")
+    return m
+
+
+def gather_features(x: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None, fp8: bool = False,
+                    status: torch.Tensor | None = None, stream=None):
+    """out[i, j] = x[i, idx[j]] for features x [n, F] and int32 indices idx [k]."""
+    n, F, ld = _rows(x)
+    if idx.dtype != torch.int32 or idx.dim() != 1 or not idx.is_contiguous():
+        raise ValueError("idx must be a contiguous 1-D int32 tensor")
+    k = idx.numel()
+    if out is None:
+        out = torch.empty((n, k), dtype=x.dtype, device=x.device)
+    if out.dim() != 2 or out.stride(1) != 1 or out.shape[0] != n or out.shape[1] < k:
+        raise ValueError("out must be a row-major [n, >= k] tensor")
+    if out.dtype != x.dtype:
+        raise TypeError("out must have the dtype of x")
+    rc = load().nb_gather_features(_ptr(x), xtype_of(x, fp8), n, F, ld, _ptr(idx), k, _ptr(out), out.stride(0),
+                                   _ptr(status), _stream(stream))
+    check(rc, "nb_gather_features")
+    return out
+
+
 def route_groups(class_counts, min_files: int = 6):
     """Model index for each size group (host logic; see include/nb.h)."""
     import numpy as np

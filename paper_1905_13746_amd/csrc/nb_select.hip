@@ -1,0 +1,438 @@
+// Per-group feature selection and feature gather on gfx950.
+//
+// Paper, section 3: each size group keeps its top-k opcodes, ranked by the
+// difference between the malware and benign programs' normalised opcode
+// occurrences; section 4: each group's model is trained and applied on those
+// k features.
+//
+//   select_kernel  one workgroup per model.  Feature f's key is the exact
+//                  integer |T_1f S_0 - T_0f S_1| (d_f scaled by S_0 S_1, at
+//                  most 94 bits) shifted up 32 bits, with F - 1 - f in the
+//                  low word: keys are distinct and a larger key is a better
+//                  feature, an exact tie going to the lower index.  A radix
+//                  select (16 passes of 8-bit digits, one LDS histogram per
+//                  pass, the digit found by a wave scan) yields the k-th
+//                  largest key; the features at or above it are written in
+//                  ascending order by a ballot compaction.  Keys are
+//                  recomputed from the counts (L2-resident) in every pass,
+//                  so any F works with 1 KB of LDS.
+//   gather_kernel  out[i][j] = x[i][idx[j]], HBM-bound: every row is read
+//                  once with 16-byte loads and k elements are written.  Each
+//                  wave stages its rows in its own LDS slice (the next rows'
+//                  loads in flight while the current ones are gathered);
+//                  each lane keeps the indices of its output positions
+//                  (j = 256 q + 4 lane + e) in registers for the whole
+//                  kernel, reads its four elements from LDS and writes them
+//                  with one packed store.  Rows longer than 8 KB, or byte
+//                  rows that are not dword aligned, are gathered straight
+//                  from global memory.
+#include <algorithm>
+
+#include "nb_device.hpp"
+#include "nb_internal.hpp"
+
+namespace nb {
+namespace {
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------------ select
+
+constexpr int kSelectBatch = 64;  // models per launch (descriptors by value)
+
+struct SelectDesc {
+  const int32_t* counts;  // [2][F]
+  const int64_t* sums;    // [2]
+  int32_t* idx;           // [k] output
+  int32_t F;
+  int32_t pad;
+};
+
+struct SelectArgs {
+  SelectDesc d[kSelectBatch];
+  int32_t n;
+  int32_t k;
+};
+
+__device__ __forceinline__ u128 select_key(const int32_t* __restrict__ counts, int F, int f, int64_t S0,
+                                           int64_t S1) {
+  const uint64_t t0 = (uint32_t)counts[f], t1 = (uint32_t)counts[F + f];
+  u128 d;
+  if (S0 == 0) {
+    d = t1;
+  } else if (S1 == 0) {
+    d = t0;
+  } else {
+    const u128 a = (u128)t1 * (uint64_t)S0;
+    const u128 b = (u128)t0 * (uint64_t)S1;
+    d = a > b ? a - b : b - a;
+  }
+  return (d << 32) | (uint32_t)(F - 1 - f);
+}
+
+__global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
+  const SelectDesc d = a.d[blockIdx.x];
+  const int F = d.F, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t S0 = d.sums[0], S1 = d.sums[1];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t found[2];
+  __shared__ uint32_t wcount[4];
+
+  u128 prefix = 0, mask = 0;
+  uint32_t rem = (uint32_t)a.k;  // rank of the wanted key among those matching prefix (1 = largest)
+  for (int shift = 120; shift >= 0; shift -= 8) {
+    hist[t] = 0;
+    __syncthreads();
+    for (int f = t; f < F; f += 256) {
+      const u128 c = select_key(d.counts, F, f, S0, S1);
+      if ((c & mask) == prefix) atomicAdd(&hist[(uint32_t)(c >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (w == 0) {
+      // lane l holds digits 255 - 4l .. 252 - 4l (descending); an inclusive
+      // scan from the top digit finds the bucket holding rank rem
+      uint32_t h[4], s = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        h[e] = hist[255 - 4 * lane - e];
+        s += h[e];
+      }
+      uint32_t inc = s;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+      }
+      const uint32_t exc = inc - s;
+      if (exc < rem && rem <= inc) {
+        uint32_t run = exc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (run < rem && rem <= run + h[e]) {
+            found[0] = (uint32_t)(255 - 4 * lane - e);
+            found[1] = rem - run;
+          }
+          run += h[e];
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t digit = found[0];
+    rem = found[1];
+    prefix |= (u128)digit << shift;
+    mask |= (u128)255u << shift;
+    __syncthreads();
+  }
+
+  // prefix is now the k-th largest key: exactly k features are >= it
+  uint32_t base = 0;
+  for (int f0 = 0; f0 < F; f0 += 256) {
+    const int f = f0 + t;
+    const bool sel = (f < F) && select_key(d.counts, F, f, S0, S1) >= prefix;
+    const uint64_t bal = __ballot(sel);
+    const uint32_t before = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t off = base;
+    for (int i = 0; i < w; ++i) off += wcount[i];
+    if (sel && off + before < (uint32_t)a.k) d.idx[off + before] = f;   // exactly k are selected
+    base += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ gather
+
+constexpr int kGatherWaves = 4;
+constexpr int kGatherThreads = 64 * kGatherWaves;
+constexpr int kRegQ = 8;               // indices held in registers: 4 * 64 * kRegQ = 2048
+constexpr int kMaxStagedRow = 8192;    // bytes of one staged row
+
+struct GatherArgs {
+  const uint8_t* x;
+  int64_t ld_bytes;
+  int64_t n;
+  int64_t total_bytes;   // bytes the input buffer holds
+  const int32_t* idx;
+  uint8_t* out;
+  int64_t ld_out_bytes;
+  int32_t* status;
+  int32_t F, k, row_bytes, row_span;  // row_span: row_bytes rounded up to 16
+  int32_t out_vec;                    // packed stores allowed (alignment)
+};
+
+// rows a wave stages together: about 4 KB of loads in flight per wave
+template <int NL>
+constexpr int gather_rows() { return NL == 0 ? 1 : (NL >= 4 ? 1 : 4 / NL); }
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Index of output position j: idx[j] if in [0, F), else -1 (and bad).
+__device__ __forceinline__ int32_t checked_index(const GatherArgs& a, int j, bool& bad) {
+  if (j >= a.k) return -1;
+  const int32_t v = a.idx[j];
+  if (v < 0 || v >= a.F) {
+    bad = true;
+    return -1;
+  }
+  return v;
+}
+
+// Write the four outputs of one lane at position j0 of row r.
+template <int ES>
+__device__ __forceinline__ void store4(const GatherArgs& a, int64_t r, int j0, const uint32_t (&v)[4]) {
+  uint8_t* orow = a.out + r * a.ld_out_bytes;
+  if (j0 + 3 < a.k && a.out_vec) {
+    if (ES == 1) {
+      const uint32_t w = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+      __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(orow + j0));
+    } else {
+      reinterpret_cast<dev::u32x4_a4*>(orow + 4 * (int64_t)j0)->v = dev::u32x4{v[0], v[1], v[2], v[3]};
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (j0 + e < a.k) {
+        if (ES == 1) orow[j0 + e] = (uint8_t)v[e];
+        else reinterpret_cast<uint32_t*>(orow)[j0 + e] = v[e];
+      }
+    }
+  }
+}
+
+// Element at byte offset o of a row (LDS or global), 0 when o < 0.
+template <int ES, class P>
+__device__ __forceinline__ uint32_t element(P row, int32_t o) {
+  if (o < 0) return 0u;
+  if (ES == 1) return row[o];
+  return reinterpret_cast<const uint32_t*>(row)[o >> 2];
+}
+
+// Gather every output of row r from `row` (staged in LDS or in global memory).
+template <int ES, bool BIGK, class P>
+__device__ __forceinline__ void emit_row(const GatherArgs& a, P row, int64_t r, int lane,
+                                         const int32_t (&off)[BIGK ? 1 : kRegQ][4], bool& bad) {
+  const int qn = (a.k + 255) >> 8;
+  if (BIGK) {
+    for (int q = 0; q < qn; ++q) {
+      const int j0 = 256 * q + 4 * lane;
+      uint32_t v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int32_t f = checked_index(a, j0 + e, bad);
+        v[e] = element<ES>(row, f < 0 ? -1 : f * ES);
+      }
+      store4<ES>(a, r, j0, v);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kRegQ; ++q) {
+      if (q < qn) {
+        uint32_t v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = element<ES>(row, off[q][e]);
+        store4<ES>(a, r, 256 * q + 4 * lane, v);
+      }
+    }
+  }
+}
+
+// NL: 1 KB loads per lane group for one row (0: no staging, global gather).
+template <int ES, int NL, bool BIGK>
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherArgs a) {
+  constexpr int RW = gather_rows<NL>();
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  bool bad = false;
+
+  // byte offsets (in a row) of this lane's outputs, -1 = none
+  int32_t off[BIGK ? 1 : kRegQ][4];
+  if (!BIGK) {
+#pragma unroll
+    for (int q = 0; q < kRegQ; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int32_t f = checked_index(a, 256 * q + 4 * lane + e, bad);
+        off[q][e] = f < 0 ? -1 : f * ES;
+      }
+  } else {
+    off[0][0] = off[0][1] = off[0][2] = off[0][3] = -1;
+  }
+
+  const int64_t gw = (int64_t)blockIdx.x * kGatherWaves + w;
+  const int64_t nw = (int64_t)gridDim.x * kGatherWaves;
+
+  if (NL == 0) {
+    for (int64_t r = gw; r < a.n; r += nw) emit_row<ES, BIGK>(a, a.x + r * a.ld_bytes, r, lane, off, bad);
+  } else {
+    constexpr int kSlot = (NL == 0 ? 1 : NL) * 1024;
+    uint8_t* buf = lds + w * (RW * kSlot);
+    const int64_t step = nw * RW;
+    dev::u32x4 v[RW][NL == 0 ? 1 : NL];
+    auto load_rows = [&](int64_t r0) {
+#pragma unroll
+      for (int s = 0; s < RW; ++s) {
+        const int64_t r = r0 + s;
+        if (r < a.n) {
+          const int64_t base = r * a.ld_bytes;
+          const int64_t avail = a.total_bytes - base;
+          if (avail >= a.row_span) {
+            const auto rsrc = dev::make_rsrc(a.x + base, avail);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+              const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
+              v[s][i] = (p < (uint32_t)a.row_bytes) ? dev::buffer_load16(rsrc, p) : dev::u32x4{0u, 0u, 0u, 0u};
+            }
+          } else {  // the buffer's last row(s): bytewise loads past its end read 0
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+              const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
+              v[s][i] = (p < (uint32_t)a.row_bytes) ? dev::load16_guarded(a.x + base + p, avail - p)
+                                                    : dev::u32x4{0u, 0u, 0u, 0u};
+            }
+          }
+        }
+      }
+    };
+    int64_t r0 = gw * RW;
+    if (r0 < a.n) load_rows(r0);
+    for (; r0 < a.n; r0 += step) {
+      wave_lds_sync();  // the previous rows' LDS reads are done
+#pragma unroll
+      for (int s = 0; s < RW; ++s)
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+          const int p = (i * 64 + lane) * 16;
+          if (p < a.row_span) *reinterpret_cast<dev::u32x4*>(buf + s * kSlot + p) = v[s][i];
+        }
+      wave_lds_sync();
+      const int64_t rn = r0 + step;
+      if (rn < a.n) load_rows(rn);
+#pragma unroll
+      for (int s = 0; s < RW; ++s)
+        if (r0 + s < a.n) emit_row<ES, BIGK>(a, buf + s * kSlot, r0 + s, lane, off, bad);
+    }
+  }
+  if (a.status && __ballot(bad) != 0ull && lane == 0) atomicOr(a.status, 1);
+}
+
+template <int ES, bool BIGK>
+const void* pick_gather(int nl) {
+  switch (nl) {
+    case 1: return reinterpret_cast<const void*>(gather_kernel<ES, 1, BIGK>);
+    case 2: return reinterpret_cast<const void*>(gather_kernel<ES, 2, BIGK>);
+    case 4: return reinterpret_cast<const void*>(gather_kernel<ES, 4, BIGK>);
+    case 8: return reinterpret_cast<const void*>(gather_kernel<ES, 8, BIGK>);
+    default: return reinterpret_cast<const void*>(gather_kernel<ES, 0, BIGK>);
+  }
+}
+
+int rows_per_wave(int nl) {
+  switch (nl) {
+    case 1: return gather_rows<1>();
+    case 2: return gather_rows<2>();
+    case 4: return gather_rows<4>();
+    case 8: return gather_rows<8>();
+    default: return gather_rows<0>();
+  }
+}
+
+}  // namespace
+}  // namespace nb
+
+using namespace nb;
+
+extern "C" {
+
+int nb_select_features(const nb_model* models, int32_t n_models, int32_t k, int32_t* idx, int64_t ld_idx,
+                       void* stream) {
+  if (n_models < 1 || !models) return fail(NB_EINVAL, "need at least one model");
+  if (!idx) return fail(NB_EINVAL, "idx must be non-NULL");
+  if (k < 1) return fail(NB_EINVAL, "k must be >= 1");
+  if (ld_idx < k) return fail(NB_EINVAL, "ld_idx must be >= k");
+  std::vector<SelectDesc> desc((size_t)n_models);
+  for (int32_t m = 0; m < n_models; ++m) {
+    nb_layout L;
+    const int rc = check_model(&models[m], &L);
+    if (rc) return rc;
+    if (models[m].n_classes != 2)
+      return fail(NB_EINVAL, "model " + std::to_string(m) + ": selection needs a two-class model");
+    if (!models[m].trained) return fail(NB_EINVAL, "model " + std::to_string(m) + " is not trained");
+    if (k > models[m].n_features)
+      return fail(NB_EINVAL, "k exceeds the feature count of model " + std::to_string(m));
+    const uint8_t* base = static_cast<const uint8_t*>(models[m].dev);
+    desc[m].counts = reinterpret_cast<const int32_t*>(base + L.off_counts);
+    desc[m].sums = reinterpret_cast<const int64_t*>(base + L.off_class_sums);
+    desc[m].idx = idx + (int64_t)m * ld_idx;
+    desc[m].F = models[m].n_features;
+    desc[m].pad = 0;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int32_t m0 = 0; m0 < n_models; m0 += kSelectBatch) {
+    SelectArgs a;
+    a.n = std::min<int32_t>(kSelectBatch, n_models - m0);
+    a.k = k;
+    for (int i = 0; i < kSelectBatch; ++i) a.d[i] = desc[(size_t)std::min<int32_t>(m0 + i, n_models - 1)];
+    hipLaunchKernelGGL(select_kernel, dim3((unsigned)a.n), dim3(256), 0, s, a);
+    NB_HIP_CHECK(hipGetLastError());
+  }
+  return NB_OK;
+}
+
+int nb_gather_features(const void* x, int32_t xtype, int64_t n, int32_t F, int64_t ld, const int32_t* idx,
+                       int32_t k, void* out, int64_t ld_out, int32_t* status, void* stream) {
+  const int es = elem_bytes(xtype);
+  if (es == 0) return fail(NB_EINVAL, "unknown feature type");
+  if (F < 1 || F > kMaxFeatures) return fail(NB_EINVAL, "n_features out of range [1, 2^20]");
+  if (k < 1 || k > kMaxFeatures) return fail(NB_EINVAL, "k out of range [1, 2^20]");
+  if (n < 0) return fail(NB_EINVAL, "n must be >= 0");
+  if (ld < F) return fail(NB_EINVAL, "ld must be >= n_features");
+  if (ld_out < k) return fail(NB_EINVAL, "ld_out must be >= k");
+  if (n == 0) return NB_OK;
+  if (!x || !idx || !out) return fail(NB_EINVAL, "x, idx and out must be non-NULL");
+  if (es == 4 && (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 3) != 0))
+    return fail(NB_EINVAL, "int32 features must be 4-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(idx) & 3) != 0) return fail(NB_EINVAL, "idx must be 4-byte aligned");
+
+  GatherArgs a;
+  a.x = static_cast<const uint8_t*>(x);
+  a.ld_bytes = ld * es;
+  a.n = n;
+  a.total_bytes = ((n - 1) * ld + F) * (int64_t)es;
+  a.idx = idx;
+  a.out = static_cast<uint8_t*>(out);
+  a.ld_out_bytes = ld_out * es;
+  a.status = status;
+  a.F = F;
+  a.k = k;
+  a.row_bytes = F * es;
+  a.row_span = (int32_t)align_up((size_t)a.row_bytes, 16);
+  a.out_vec = ((reinterpret_cast<uintptr_t>(out) & 3) == 0 && (a.ld_out_bytes & 3) == 0) ? 1 : 0;
+
+  const bool aligned = ((reinterpret_cast<uintptr_t>(x) & 3) == 0) && ((a.ld_bytes & 3) == 0);
+  int nl = 0;
+  if (aligned && a.row_span <= kMaxStagedRow) {
+    nl = 1;
+    while (nl * 1024 < a.row_span) nl *= 2;
+  }
+  const bool bigk = k > 4 * 64 * kRegQ;
+  const void* fn = (es == 1) ? (bigk ? pick_gather<1, true>(nl) : pick_gather<1, false>(nl))
+                             : (bigk ? pick_gather<4, true>(nl) : pick_gather<4, false>(nl));
+  const int rw = rows_per_wave(nl);
+  const size_t lds = nl ? (size_t)kGatherWaves * rw * nl * 1024 : 0;
+  const int64_t rows_per_wg = (int64_t)kGatherWaves * rw;
+  const int64_t need = (n + rows_per_wg - 1) / rows_per_wg;
+  const int64_t cap = (int64_t)resident_per_cu(fn, kGatherThreads, lds) * device_cu_count();
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(need, cap));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  void* args[] = {&a};
+  NB_HIP_CHECK(hipLaunchKernel(fn, dim3(grid), dim3(kGatherThreads), args, lds, s));
+  return NB_OK;
+}
+
+}  // extern "C"

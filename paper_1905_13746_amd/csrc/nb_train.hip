@@ -344,6 +344,7 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
   const int any_over = __syncthreads_or(over);
   const int any_bad = __syncthreads_or(fl & kFlagBadLabel);
   const int any_neg = __syncthreads_or(fl & kFlagNegative);
+  const int any_idx = __syncthreads_or(fl & kFlagBadIndex);
   // class totals: one partial per thread, summed in a fixed order
   __shared__ int64_t snc[kMaxClasses];
   if (t < a.C) {
@@ -364,7 +365,8 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
     a.class_totals[c] = Nc;
     a.class_sums[c] = (a.kind == NB_MULTINOMIAL) ? Sc : Nc;
     a.class_flags[c] = (any_over ? kFlagOverflow : 0) | ((Nc < a.min_files || Nc < 1) ? kFlagMinFiles : 0) |
-                       (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0);
+                       (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0) |
+                       (any_idx ? kFlagBadIndex : 0);
   }
 
   const double al = a.alpha;
@@ -496,7 +498,93 @@ TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
   return w;
 }
 
+// A k-feature model from a trained model's counts (the model trained on the
+// gathered columns): the selected columns become the single second-level
+// partial of class_tables, the class totals are copied, and an index outside
+// [0, F) is flagged (its column reads as 0).  grid (ceil(k/256), C).
+__global__ __launch_bounds__(256) void subset_counts(const int32_t* __restrict__ counts,
+                                                    const int64_t* __restrict__ totals,
+                                                    const int32_t* __restrict__ idx, int F, int k, int Fp_out,
+                                                    int64_t* __restrict__ part2, int64_t* __restrict__ nc2,
+                                                    int32_t* __restrict__ flag_part) {
+  const int c = blockIdx.y, t = threadIdx.x;
+  const int j = blockIdx.x * 256 + t;
+  bool bad = false;
+  if (j < k) {
+    const int32_t f = idx[j];
+    int64_t v = 0;
+    if (f < 0 || f >= F) bad = true;
+    else v = counts[(int64_t)c * F + f];
+    part2[(int64_t)c * Fp_out + j] = v;
+  }
+  const int any_bad = __syncthreads_or(bad);
+  if (t == 0) {
+    flag_part[(int64_t)c * gridDim.x + blockIdx.x] = any_bad ? kFlagBadIndex : 0;
+    if (blockIdx.x == 0) nc2[c] = totals[c];
+  }
+}
+
+// Workspace of nb_model_select: part2 [C][Fp], nc2 [C], flags.
+struct SelectWs {
+  int32_t n_flags;
+  size_t off_part2, off_nc2, off_flags, total;
+};
+
+SelectWs select_ws(int32_t C, int32_t k, int32_t Fp) {
+  SelectWs w;
+  w.n_flags = C * ((k + 255) / 256);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, kAlign);
+    return at;
+  };
+  w.off_part2 = take((size_t)C * Fp * 8);
+  w.off_nc2 = take((size_t)C * 8);
+  w.off_flags = take(((size_t)w.n_flags + C) * 4);
+  w.total = off;
+  return w;
+}
+
+// Table build shared by nb_train and nb_model_select: class_tables over RS
+// second-level partials, then the scoring rows and the status word.
+int launch_tables(nb_model* m, const nb_layout& L, const int64_t* part2, const int64_t* nc2, int RS,
+                  const int32_t* flag_part, int n_flags, int32_t* class_flags, double alpha, int min_files,
+                  hipStream_t s) {
+  uint8_t* base = static_cast<uint8_t*>(m->dev);
+  TableArgs ta;
+  ta.part2 = part2;
+  ta.nc2 = nc2;
+  ta.counts = reinterpret_cast<int32_t*>(base + L.off_counts);
+  ta.class_totals = reinterpret_cast<int64_t*>(base + L.off_class_totals);
+  ta.class_sums = reinterpret_cast<int64_t*>(base + L.off_class_sums);
+  ta.log_theta = reinterpret_cast<double*>(base + L.off_log_theta);
+  ta.log_1m_theta = reinterpret_cast<double*>(base + L.off_log_1m_theta);
+  ta.weight = reinterpret_cast<double*>(base + L.off_weight);
+  ta.bias = reinterpret_cast<double*>(base + L.off_bias);
+  ta.flag_part = flag_part;
+  ta.class_flags = class_flags;
+  ta.n_flags = n_flags;
+  ta.alpha = alpha;
+  ta.F = m->n_features;
+  ta.C = m->n_classes;
+  ta.Fp = L.padded_features;
+  ta.RS = RS;
+  ta.kind = m->kind;
+  ta.min_files = min_files;
+  hipLaunchKernelGGL(class_tables, dim3((unsigned)ta.C), dim3(256), 0, s, ta);
+  NB_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(form_rows, dim3((unsigned)(ta.Fp / 256)), dim3(256), 0, s, ta.weight, ta.bias, ta.C, ta.F,
+                     ta.Fp, reinterpret_cast<float*>(base + L.off_form_f32),
+                     reinterpret_cast<uint16_t*>(base + L.off_form_bf16),
+                     reinterpret_cast<float*>(base + L.off_form_bias), class_flags,
+                     reinterpret_cast<int32_t*>(base + L.off_status));
+  NB_HIP_CHECK(hipGetLastError());
+  return NB_OK;
+}
+
 int flags_to_status(int32_t flags) {
+  if (flags & kFlagBadIndex) return fail(NB_EDATA, "a selected feature index is outside [0, F)");
   if (flags & (kFlagBadLabel | kFlagNegative))
     return fail(NB_EDATA, (flags & kFlagBadLabel) ? "a label is outside [0, C)" : "a feature value is negative");
   if (flags & kFlagOverflow) return fail(NB_EOVERFLOW, "a per-class count exceeds INT32_MAX");
@@ -585,37 +673,58 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
                      part, nc_part, (int)S, C, F, Fp, part2, nc2);
   NB_HIP_CHECK(hipGetLastError());
 
-  TableArgs ta;
-  ta.part2 = part2;
-  ta.nc2 = nc2;
-  ta.counts = reinterpret_cast<int32_t*>(base + L.off_counts);
-  ta.class_totals = reinterpret_cast<int64_t*>(base + L.off_class_totals);
-  ta.class_sums = reinterpret_cast<int64_t*>(base + L.off_class_sums);
-  ta.log_theta = reinterpret_cast<double*>(base + L.off_log_theta);
-  ta.log_1m_theta = reinterpret_cast<double*>(base + L.off_log_1m_theta);
-  ta.weight = reinterpret_cast<double*>(base + L.off_weight);
-  ta.bias = reinterpret_cast<double*>(base + L.off_bias);
-  ta.flag_part = flag_part;
-  ta.class_flags = class_flags;
-  ta.n_flags = n_flags;
-  ta.alpha = alpha;
-  ta.F = F;
-  ta.C = C;
-  ta.Fp = Fp;
-  ta.RS = (int32_t)tw.RS;
-  ta.kind = m->kind;
-  ta.min_files = min_files_per_class;
-  hipLaunchKernelGGL(class_tables, dim3((unsigned)C), dim3(256), 0, s, ta);
-  NB_HIP_CHECK(hipGetLastError());
-
-  hipLaunchKernelGGL(form_rows, dim3((unsigned)(Fp / 256)), dim3(256), 0, s, ta.weight, ta.bias, C, F, Fp,
-                     reinterpret_cast<float*>(base + L.off_form_f32),
-                     reinterpret_cast<uint16_t*>(base + L.off_form_bf16),
-                     reinterpret_cast<float*>(base + L.off_form_bias), class_flags, status);
-  NB_HIP_CHECK(hipGetLastError());
+  rc = launch_tables(m, L, part2, nc2, (int)tw.RS, flag_part, n_flags, class_flags, alpha, min_files_per_class,
+                     s);
+  if (rc) return rc;
 
   if (flags & NB_TRAIN_ASYNC) return NB_OK;
   return nb_model_status(m, stream);
+}
+
+size_t nb_model_select_workspace_bytes(int32_t n_classes, int32_t k) {
+  nb_layout L;
+  if (!compute_layout(n_classes, k, &L)) return 0;
+  return select_ws(n_classes, k, L.padded_features).total;
+}
+
+int nb_model_select(const nb_model* full, const int32_t* idx, int32_t k, double alpha, nb_model* out,
+                    void* workspace, size_t workspace_bytes, int32_t flags, void* stream) {
+  nb_layout LF, L;
+  int rc = check_model(full, &LF);
+  if (rc) return rc;
+  if (!full->trained) return fail(NB_EINVAL, "the full model is not trained");
+  if (!out) return fail(NB_EINVAL, "out is NULL");
+  if (out->n_features != k) return fail(NB_EINVAL, "out->n_features must equal k");
+  if (out->kind != full->kind || out->n_classes != full->n_classes)
+    return fail(NB_EINVAL, "out must have the kind and class count of the full model");
+  rc = check_model(out, &L);
+  if (rc) return rc;
+  if (out->dev == full->dev) return fail(NB_EINVAL, "out must have its own buffer");
+  out->trained = 0;
+  if (!idx) return fail(NB_EINVAL, "idx must be non-NULL");
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(NB_EINVAL, "alpha must be finite and > 0");
+  const int C = full->n_classes;
+  const SelectWs w = select_ws(C, k, L.padded_features);
+  if (!workspace || workspace_bytes < w.total)
+    return fail(NB_ENOMEM, "workspace smaller than nb_model_select_workspace_bytes()");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0) return fail(NB_EINVAL, "workspace must be 8-byte aligned");
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint8_t* wsb = static_cast<uint8_t*>(workspace);
+  int64_t* part2 = reinterpret_cast<int64_t*>(wsb + w.off_part2);
+  int64_t* nc2 = reinterpret_cast<int64_t*>(wsb + w.off_nc2);
+  int32_t* flag_part = reinterpret_cast<int32_t*>(wsb + w.off_flags);
+  int32_t* class_flags = flag_part + w.n_flags;
+  const uint8_t* fb = static_cast<const uint8_t*>(full->dev);
+  hipLaunchKernelGGL(subset_counts, dim3((unsigned)((k + 255) / 256), (unsigned)C), dim3(256), 0, s,
+                     reinterpret_cast<const int32_t*>(fb + LF.off_counts),
+                     reinterpret_cast<const int64_t*>(fb + LF.off_class_totals), idx, full->n_features, k,
+                     L.padded_features, part2, nc2, flag_part);
+  NB_HIP_CHECK(hipGetLastError());
+  rc = launch_tables(out, L, part2, nc2, 1, flag_part, w.n_flags, class_flags, alpha, 1, s);
+  if (rc) return rc;
+  if (flags & NB_TRAIN_ASYNC) return NB_OK;
+  return nb_model_status(out, stream);
 }
 
 int nb_model_status(nb_model* m, void* stream) {

@@ -198,3 +198,56 @@ def test_group_plan_rejects_before_allocating(lib):
     assert lib.nb_group_plan_create(cm, 1, cg, 1, 0, 0, 0, 2 | 4, None, ctypes.byref(out)) == -1  # two schedules
     assert lib.nb_group_plan_destroy(None) == 0
     assert lib.nb_group_plan_launch(None, None) == -1
+
+
+def test_selection_argument_errors(lib):
+    """Feature selection, k-feature models and the gather validate their
+    arguments before touching a device."""
+    trained = _model(2, 100)
+    trained.trained = 1
+    arr = (_lib.NbModel * 1)(trained)
+    idx = ctypes.c_void_p(FAKE_DEV)
+    assert lib.nb_select_features(arr, 0, 5, idx, 5, None) == -1          # no models
+    assert lib.nb_select_features(arr, 1, 5, None, 5, None) == -1         # idx NULL
+    assert lib.nb_select_features(arr, 1, 0, idx, 5, None) == -1          # k < 1
+    assert lib.nb_select_features(arr, 1, 5, idx, 4, None) == -1          # ld_idx < k
+    assert lib.nb_select_features(arr, 1, 101, idx, 101, None) == -1      # k > F
+    untrained = (_lib.NbModel * 1)(_model(2, 100))
+    assert lib.nb_select_features(untrained, 1, 5, idx, 5, None) == -1
+    three = _model(3, 100)
+    three.trained = 1
+    assert lib.nb_select_features((_lib.NbModel * 1)(three), 1, 5, idx, 5, None) == -1
+
+    assert lib.nb_model_select_workspace_bytes(2, 200) > 0
+    assert lib.nb_model_select_workspace_bytes(1, 200) == 0
+    assert lib.nb_model_select_workspace_bytes(2, 0) == 0
+    ws = ctypes.c_void_p(FAKE_DEV)
+    big = 1 << 30
+    out = _lib.NbModel(0, 2, 7, 0, FAKE_DEV + (1 << 20))
+    assert lib.nb_model_select(ctypes.byref(_model(2, 100)), idx, 7, 1.0, ctypes.byref(out), ws, big, 0,
+                               None) == -1                                # full not trained
+    assert lib.nb_model_select(ctypes.byref(trained), idx, 8, 1.0, ctypes.byref(out), ws, big, 0, None) == -1
+    other_kind = _lib.NbModel(1, 2, 7, 0, FAKE_DEV + (1 << 20))
+    assert lib.nb_model_select(ctypes.byref(trained), idx, 7, 1.0, ctypes.byref(other_kind), ws, big, 0,
+                               None) == -1
+    same_buf = _lib.NbModel(0, 2, 7, 0, FAKE_DEV)
+    assert lib.nb_model_select(ctypes.byref(trained), idx, 7, 1.0, ctypes.byref(same_buf), ws, big, 0,
+                               None) == -1
+    assert lib.nb_model_select(ctypes.byref(trained), None, 7, 1.0, ctypes.byref(out), ws, big, 0, None) == -1
+    assert lib.nb_model_select(ctypes.byref(trained), idx, 7, 0.0, ctypes.byref(out), ws, big, 0, None) == -1
+    assert lib.nb_model_select(ctypes.byref(trained), idx, 7, 1.0, ctypes.byref(out), ws, 16, 0, None) == -6
+
+    x = ctypes.c_void_p(FAKE_DEV)
+    o = ctypes.c_void_p(FAKE_DEV + (1 << 24))
+    g = lib.nb_gather_features
+    assert g(x, 7, 10, 100, 100, idx, 5, o, 5, None, None) == -1          # unknown type
+    assert g(x, 0, 10, 0, 100, idx, 5, o, 5, None, None) == -1            # F < 1
+    assert g(x, 0, 10, 100, 100, idx, 0, o, 5, None, None) == -1          # k < 1
+    assert g(x, 0, -1, 100, 100, idx, 5, o, 5, None, None) == -1          # n < 0
+    assert g(x, 0, 10, 100, 99, idx, 5, o, 5, None, None) == -1           # ld < F
+    assert g(x, 0, 10, 100, 100, idx, 5, o, 4, None, None) == -1          # ld_out < k
+    assert g(None, 0, 0, 100, 100, None, 5, None, 5, None, None) == 0     # n == 0: no-op
+    assert g(None, 0, 10, 100, 100, idx, 5, o, 5, None, None) == -1       # x NULL
+    assert g(x, 0, 10, 100, 100, None, 5, o, 5, None, None) == -1         # idx NULL
+    assert g(ctypes.c_void_p(FAKE_DEV + 2), 1, 10, 100, 100, idx, 5, o, 5, None, None) == -1  # int32 misaligned
+    assert g(x, 0, 10, 100, 100, ctypes.c_void_p(FAKE_DEV + 2), 5, o, 5, None, None) == -1    # idx misaligned

@@ -59,9 +59,11 @@ def parse():
                     help="repeat the oracle's step until this much CPU time has been spent")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--leg", choices=["f_sweep", "precision", "groups", "serve"],
+    ap.add_argument("--leg", choices=["f_sweep", "precision", "groups", "serve", "select"],
                     help="run only this extra leg and print its JSON (used for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--select-k", default="20,40,80,100,160,200",
+                    help="k values of the select leg (comma separated)")
     ap.add_argument("--fill-inputs", action="store_true",
                     help="constant-filled inputs instead of the seeded generator (for hardware-counter runs: "
                          "the kernels' memory traffic does not depend on feature values)")
@@ -270,6 +272,56 @@ def groups_leg(nbg, W, steps: int = 20):
     return res
 
 
+def select_leg(nbg, W, n_files: int = 1_000_000, F: int = 2000, steps: int = 20,
+               ks=(20, 40, 80, 100, 160, 200), fill: bool = False):
+    """Per-group top-k feature selection and the feature gather: selection
+    over 256 two-class models of F = 2000 features, the k-feature model built
+    from counts, the gather of a million F = 2000 byte rows to their top k
+    columns for the paper's k values, and scoring of the k-column rows."""
+    models = []
+    for g in range(256):
+        wl = W.group_workload(g, F)
+        if fill:
+            X = torch.full((600, F), 1 + g % 3, dtype=torch.uint8, device="cuda")
+            y = (torch.arange(600, device="cuda") % 2).to(torch.int32)
+        else:
+            X, y = wl.train_set(600, device="cuda")
+        m = nbg.Model(2, F, "multinomial")
+        nbg.train(m, X, y)
+        models.append(m)
+        del X, y
+    idx = torch.empty((256, 200), dtype=torch.int32, device="cuda")
+    ms_select = timed(lambda: nbg.select_features(models, 200, out=idx), steps)
+    wl = W.group_workload(0, F)
+    if fill:
+        Xt = torch.full((n_files, F), 2, dtype=torch.uint8, device="cuda")
+    else:
+        Xt, _ = wl.test_set(n_files, device="cuda")
+    n = n_files
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    lp = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    ms_full = timed(lambda: nbg.score(models[0], Xt, out=(lab, lp, None)), steps)
+    per_k = {}
+    for k in ks:
+        ik = nbg.select_features([models[0]], k)[0].contiguous()
+        mk = nbg.Model(2, k, "multinomial")
+        ws = torch.empty(nbg.load().nb_model_select_workspace_bytes(2, k), dtype=torch.uint8, device="cuda")
+        ms_model = timed(lambda: nbg.model_on_features(models[0], ik, workspace=ws, out=mk), steps)
+        out = torch.empty((n, k), dtype=torch.uint8, device="cuda")
+        ms_gather = timed(lambda: nbg.gather_features(Xt, ik, out=out), steps)
+        ms_score = timed(lambda: nbg.score(mk, out, out=(lab, lp, None)), steps)
+        gb = n * (F + k) / (ms_gather / 1e3) / 1e9
+        per_k[str(k)] = {"gather_ms": ms_gather, "gather_GBps": gb, "gather_frac_of_peak": gb / HBM_PEAK_GBPS,
+                         "score_k_ms": ms_score, "score_k_files_per_s": n / (ms_score / 1e3),
+                         "k_model_from_counts_ms": ms_model}
+        del out
+    return {"workload": f"256 two-class multinomial models of F={F} uint8 features (600 training files each); "
+                        f"gather and scoring over {n} files of F={F} uint8 (group 0's distribution)",
+            "select_256_models_k200_ms": ms_select, "score_full_F_ms": ms_full,
+            "score_full_F_files_per_s": n / (ms_full / 1e3), "per_k": per_k,
+            "gather_algorithmic_bytes_per_file": f"F + k = {F} + k (each row read once, k bytes written)"}
+
+
 def serve_leg(nbg, W, n_requests: int = 8000, full: bool = False):
     """Continuous-batching server on the 8-model request mix.  full: the
     whole sweep (0.1 .. 1.2 of saturation plus fixed rates) at 20,000
@@ -362,7 +414,8 @@ def main():
         if args.leg == "precision":
             res = precision_compare(nbg, W, fill=args.fill_inputs)
         else:
-            res = {"f_sweep": f_sweep, "groups": groups_leg,
+            ks = tuple(int(v) for v in args.select_k.split(","))
+            res = {"f_sweep": f_sweep, "groups": groups_leg, "select": lambda a, b: select_leg(a, b, ks=ks, fill=args.fill_inputs),
                    "serve": lambda a, b: serve_leg(a, b, full=True)}[args.leg](nbg, W)
         print(json.dumps({"leg": args.leg, **res}), flush=True)
         return
@@ -458,6 +511,8 @@ def main():
         rec["groups"] = groups_leg(nbg, W)
         torch.cuda.empty_cache()
         rec["serve"] = serve_leg(nbg, W)
+        torch.cuda.empty_cache()
+        rec["select"] = select_leg(nbg, W)
         rec["paper_context"] = ("the paper reports up to 200x GPU over a sequential CPU program on a GTX 1050 Ti "
                                 "vs an i7-7700HQ, overheads excluded (section 4); different hardware and workload")
     print(json.dumps(rec), flush=True)

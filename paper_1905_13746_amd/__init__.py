@@ -175,13 +175,13 @@ def select_features(models, k: int, out: torch.Tensor | None = None, stream=None
 
 
 def model_on_features(full: Model, idx: torch.Tensor, alpha: float = 1.0, workspace: torch.Tensor | None = None,
-                      asynchronous: bool = False, stream=None) -> Model:
+                      asynchronous: bool = False, out: Model | None = None, stream=None) -> Model:
     """The model trained on the features idx (int32, device), built from
-    full's counts without its training files."""
+    full's counts without its training files (into `out` when given)."""
     if idx.dtype != torch.int32 or idx.dim() != 1 or not idx.is_contiguous():
         raise ValueError("idx must be a contiguous 1-D int32 tensor")
     k = idx.numel()
-    m = Model(full.n_classes, k, full.kind, device=full.buf.device)
+    m = out if out is not None else Model(full.n_classes, k, full.kind, device=full.buf.device)
     if workspace is None:
         nbytes = load().nb_model_select_workspace_bytes(full.n_classes, k)
         workspace = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=full.buf.device)

@@ -18,8 +18,9 @@
 //                  so any F works with 1 KB of LDS.
 //   gather_kernel  out[i][j] = x[i][idx[j]], HBM-bound: every row is read
 //                  once with 16-byte loads and k elements are written.  Each
-//                  wave stages its rows in its own LDS slice (the next rows'
-//                  loads in flight while the current ones are gathered);
+//                  wave stages its rows in its own LDS slice (the loads of
+//                  its next two row batches in flight while the current one
+//                  is gathered);
 //                  each lane keeps the indices of its output positions
 //                  (j = 256 q + 4 lane + e) in registers for the whole
 //                  kernel, reads its four elements from LDS and writes them
@@ -212,12 +213,14 @@ __device__ __forceinline__ uint32_t element(P row, int32_t o) {
   return reinterpret_cast<const uint32_t*>(row)[o >> 2];
 }
 
-// Gather every output of row r from `row` (staged in LDS or in global memory).
-template <int ES, bool BIGK, class P>
+// Gather every output of row r from `row` (staged in LDS or in global
+// memory).  Q > 0: this lane's byte offsets are in off[Q][4]; Q == 0: the
+// indices are read (and checked) per row.
+template <int ES, int Q, class P>
 __device__ __forceinline__ void emit_row(const GatherArgs& a, P row, int64_t r, int lane,
-                                         const int32_t (&off)[BIGK ? 1 : kRegQ][4], bool& bad) {
+                                         const int32_t (&off)[Q == 0 ? 1 : Q][4], bool& bad) {
   const int qn = (a.k + 255) >> 8;
-  if (BIGK) {
+  if (Q == 0) {
     for (int q = 0; q < qn; ++q) {
       const int j0 = 256 * q + 4 * lane;
       uint32_t v[4];
@@ -230,7 +233,7 @@ __device__ __forceinline__ void emit_row(const GatherArgs& a, P row, int64_t r, 
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < kRegQ; ++q) {
+    for (int q = 0; q < (Q == 0 ? 1 : Q); ++q) {
       if (q < qn) {
         uint32_t v[4];
 #pragma unroll
@@ -241,94 +244,127 @@ __device__ __forceinline__ void emit_row(const GatherArgs& a, P row, int64_t r, 
   }
 }
 
-// NL: 1 KB loads per lane group for one row (0: no staging, global gather).
-template <int ES, int NL, bool BIGK>
+// NL: 1 KB loads of a row per wave (0: no staging, gather from global
+// memory).  Q: 256-index groups held in registers (0: read per row).
+// A unit is RW consecutive rows; wave w takes units w, w + nw, ... and keeps
+// the loads of the next two units in flight (three register buffers) while
+// it stages and gathers the current one.
+template <int ES, int NL, int Q>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherArgs a) {
   constexpr int RW = gather_rows<NL>();
+  constexpr int NLB = NL == 0 ? 1 : NL;
+  constexpr int QB = Q == 0 ? 1 : Q;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   bool bad = false;
 
   // byte offsets (in a row) of this lane's outputs, -1 = none
-  int32_t off[BIGK ? 1 : kRegQ][4];
-  if (!BIGK) {
+  int32_t off[QB][4];
 #pragma unroll
-    for (int q = 0; q < kRegQ; ++q)
+  for (int q = 0; q < QB; ++q)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int32_t f = checked_index(a, 256 * q + 4 * lane + e, bad);
-        off[q][e] = f < 0 ? -1 : f * ES;
-      }
-  } else {
-    off[0][0] = off[0][1] = off[0][2] = off[0][3] = -1;
-  }
+    for (int e = 0; e < 4; ++e) {
+      const int32_t f = (Q == 0) ? -1 : checked_index(a, 256 * q + 4 * lane + e, bad);
+      off[q][e] = f < 0 ? -1 : f * ES;
+    }
 
   const int64_t gw = (int64_t)blockIdx.x * kGatherWaves + w;
   const int64_t nw = (int64_t)gridDim.x * kGatherWaves;
 
   if (NL == 0) {
-    for (int64_t r = gw; r < a.n; r += nw) emit_row<ES, BIGK>(a, a.x + r * a.ld_bytes, r, lane, off, bad);
+    for (int64_t r = gw; r < a.n; r += nw) emit_row<ES, Q>(a, a.x + r * a.ld_bytes, r, lane, off, bad);
   } else {
-    constexpr int kSlot = (NL == 0 ? 1 : NL) * 1024;
+    constexpr int kSlot = NLB * 1024;
     uint8_t* buf = lds + w * (RW * kSlot);
-    const int64_t step = nw * RW;
-    dev::u32x4 v[RW][NL == 0 ? 1 : NL];
-    auto load_rows = [&](int64_t r0) {
+    const int64_t nunits = (a.n + RW - 1) / RW;
+    const int64_t mine = gw < nunits ? (nunits - 1 - gw) / nw + 1 : 0;
+    auto issue = [&](int64_t t, dev::u32x4 (&dst)[RW][NLB]) {
+      if (t < mine) {
+        const int64_t r0 = (gw + t * nw) * RW;
 #pragma unroll
-      for (int s = 0; s < RW; ++s) {
-        const int64_t r = r0 + s;
-        if (r < a.n) {
-          const int64_t base = r * a.ld_bytes;
-          const int64_t avail = a.total_bytes - base;
-          if (avail >= a.row_span) {
-            const auto rsrc = dev::make_rsrc(a.x + base, avail);
+        for (int s = 0; s < RW; ++s) {
+          const int64_t r = r0 + s;
+          if (r < a.n) {
+            const int64_t base = r * a.ld_bytes;
+            const int64_t avail = a.total_bytes - base;
+            if (avail >= a.row_span) {
+              const auto rsrc = dev::make_rsrc(a.x + base, avail);
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-              const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
-              v[s][i] = (p < (uint32_t)a.row_bytes) ? dev::buffer_load16(rsrc, p) : dev::u32x4{0u, 0u, 0u, 0u};
-            }
-          } else {  // the buffer's last row(s): bytewise loads past its end read 0
+              for (int i = 0; i < NLB; ++i) {
+                const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
+                dst[s][i] = (p < (uint32_t)a.row_bytes) ? dev::buffer_load16(rsrc, p)
+                                                        : dev::u32x4{0u, 0u, 0u, 0u};
+              }
+            } else {  // the buffer's last row(s): bytes past its end read 0
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-              const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
-              v[s][i] = (p < (uint32_t)a.row_bytes) ? dev::load16_guarded(a.x + base + p, avail - p)
-                                                    : dev::u32x4{0u, 0u, 0u, 0u};
+              for (int i = 0; i < NLB; ++i) {
+                const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
+                dst[s][i] = (p < (uint32_t)a.row_bytes) ? dev::load16_guarded(a.x + base + p, avail - p)
+                                                        : dev::u32x4{0u, 0u, 0u, 0u};
+              }
             }
           }
         }
       }
+      __builtin_amdgcn_sched_barrier(0);
     };
-    int64_t r0 = gw * RW;
-    if (r0 < a.n) load_rows(r0);
-    for (; r0 < a.n; r0 += step) {
-      wave_lds_sync();  // the previous rows' LDS reads are done
+    auto consume = [&](int64_t t, const dev::u32x4 (&src)[RW][NLB]) {
+      const int64_t r0 = (gw + t * nw) * RW;
+      wave_lds_sync();  // the previous unit's LDS reads are done
 #pragma unroll
       for (int s = 0; s < RW; ++s)
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
+        for (int i = 0; i < NLB; ++i) {
           const int p = (i * 64 + lane) * 16;
-          if (p < a.row_span) *reinterpret_cast<dev::u32x4*>(buf + s * kSlot + p) = v[s][i];
+          if (p < a.row_span) *reinterpret_cast<dev::u32x4*>(buf + s * kSlot + p) = src[s][i];
         }
       wave_lds_sync();
-      const int64_t rn = r0 + step;
-      if (rn < a.n) load_rows(rn);
 #pragma unroll
       for (int s = 0; s < RW; ++s)
-        if (r0 + s < a.n) emit_row<ES, BIGK>(a, buf + s * kSlot, r0 + s, lane, off, bad);
+        if (r0 + s < a.n) emit_row<ES, Q>(a, buf + s * kSlot, r0 + s, lane, off, bad);
+    };
+    if (mine > 0) {
+      dev::u32x4 b0[RW][NLB], b1[RW][NLB], b2[RW][NLB];
+      issue(0, b0);
+      issue(1, b1);
+      for (int64_t t = 0;; t += 3) {
+        issue(t + 2, b2);
+        consume(t, b0);
+        if (t + 1 >= mine) break;
+        issue(t + 3, b0);
+        consume(t + 1, b1);
+        if (t + 2 >= mine) break;
+        issue(t + 4, b1);
+        consume(t + 2, b2);
+        if (t + 3 >= mine) break;
+      }
     }
   }
   if (a.status && __ballot(bad) != 0ull && lane == 0) atomicOr(a.status, 1);
 }
 
-template <int ES, bool BIGK>
-const void* pick_gather(int nl) {
+template <int ES, int Q>
+const void* pick_gather_nl(int nl) {
   switch (nl) {
-    case 1: return reinterpret_cast<const void*>(gather_kernel<ES, 1, BIGK>);
-    case 2: return reinterpret_cast<const void*>(gather_kernel<ES, 2, BIGK>);
-    case 4: return reinterpret_cast<const void*>(gather_kernel<ES, 4, BIGK>);
-    case 8: return reinterpret_cast<const void*>(gather_kernel<ES, 8, BIGK>);
-    default: return reinterpret_cast<const void*>(gather_kernel<ES, 0, BIGK>);
+    case 1: return reinterpret_cast<const void*>(gather_kernel<ES, 1, Q>);
+    case 2: return reinterpret_cast<const void*>(gather_kernel<ES, 2, Q>);
+    case 4: return reinterpret_cast<const void*>(gather_kernel<ES, 4, Q>);
+    case 8: return reinterpret_cast<const void*>(gather_kernel<ES, 8, Q>);
+    default: return reinterpret_cast<const void*>(gather_kernel<ES, 0, Q>);
+  }
+}
+
+// Index groups held in registers for k outputs: 1, 2 or 8 (0: k > 2048).
+int gather_q(int32_t k) { return k <= 256 ? 1 : (k <= 512 ? 2 : (k <= 4 * 64 * kRegQ ? 8 : 0)); }
+
+template <int ES>
+const void* pick_gather(int nl, int q) {
+  switch (q) {
+    case 1: return pick_gather_nl<ES, 1>(nl);
+    case 2: return pick_gather_nl<ES, 2>(nl);
+    case 8: return pick_gather_nl<ES, 8>(nl);
+    default: return pick_gather_nl<ES, 0>(nl);
   }
 }
 
@@ -420,9 +456,8 @@ int nb_gather_features(const void* x, int32_t xtype, int64_t n, int32_t F, int64
     nl = 1;
     while (nl * 1024 < a.row_span) nl *= 2;
   }
-  const bool bigk = k > 4 * 64 * kRegQ;
-  const void* fn = (es == 1) ? (bigk ? pick_gather<1, true>(nl) : pick_gather<1, false>(nl))
-                             : (bigk ? pick_gather<4, true>(nl) : pick_gather<4, false>(nl));
+  const int q = gather_q(k);
+  const void* fn = (es == 1) ? pick_gather<1>(nl, q) : pick_gather<4>(nl, q);
   const int rw = rows_per_wave(nl);
   const size_t lds = nl ? (size_t)kGatherWaves * rw * nl * 1024 : 0;
   const int64_t rows_per_wg = (int64_t)kGatherWaves * rw;

@@ -18,15 +18,19 @@
 //                  so any F works with 1 KB of LDS.
 //   gather_kernel  out[i][j] = x[i][idx[j]], HBM-bound: every row is read
 //                  once with 16-byte loads and k elements are written.  Each
-//                  wave stages its rows in its own LDS slice (the loads of
-//                  its next two row batches in flight while the current one
-//                  is gathered);
+//                  wave stages units of consecutive rows, each loaded as one
+//                  contiguous span from a 16-byte boundary, in its own LDS
+//                  slice (the loads of its next two units in flight while
+//                  the current one is gathered);
 //                  each lane keeps the indices of its output positions
 //                  (j = 256 q + 4 lane + e) in registers for the whole
 //                  kernel, reads its four elements from LDS and writes them
-//                  with one packed store.  Rows longer than 8 KB, or byte
-//                  rows that are not dword aligned, are gathered straight
-//                  from global memory.
+//                  with one packed store; every load and store is issued
+//                  unconditionally (absent lanes go out of the buffer
+//                  range), so waiting for one unit never waits for the two
+//                  behind it.  Rows longer than 8 KB, rows or outputs that
+//                  are not dword aligned, and more than 2048 indices are
+//                  gathered straight from global memory.
 #include <algorithm>
 
 #include "nb_device.hpp"
@@ -147,7 +151,15 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
 constexpr int kGatherWaves = 4;
 constexpr int kGatherThreads = 64 * kGatherWaves;
 constexpr int kRegQ = 8;               // indices held in registers: 4 * 64 * kRegQ = 2048
-constexpr int kMaxStagedRow = 8192;    // bytes of one staged row
+constexpr int kMaxStagedRow = 8192;    // bytes of the longest staged row (plus its lead)
+// Bytes of a unit: the contiguous span of rows a wave stages at once (two
+// units' loads in flight per wave; 8 KB measured faster than 4 KB for rows
+// of 1000 to 5000 bytes); 8 KB for rows too long for a smaller unit.
+#ifndef NB_GATHER_UNIT_KB
+#define NB_GATHER_UNIT_KB 8
+#endif
+constexpr int kGatherUnitKB = NB_GATHER_UNIT_KB;
+constexpr uint32_t kOutOfRange = 0x80000000u;  // buffer offset past any range: no access
 
 struct GatherArgs {
   const uint8_t* x;
@@ -158,13 +170,10 @@ struct GatherArgs {
   uint8_t* out;
   int64_t ld_out_bytes;
   int32_t* status;
-  int32_t F, k, row_bytes, row_span;  // row_span: row_bytes rounded up to 16
-  int32_t out_vec;                    // packed stores allowed (alignment)
+  int64_t nfast;         // leading units whose whole span lies inside the buffer
+  int32_t F, k, row_bytes;
+  int32_t out_vec;       // packed stores allowed (alignment)
 };
-
-// rows a wave stages together: about 4 KB of loads in flight per wave
-template <int NL>
-constexpr int gather_rows() { return NL == 0 ? 1 : (NL >= 4 ? 1 : 4 / NL); }
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -183,7 +192,9 @@ __device__ __forceinline__ int32_t checked_index(const GatherArgs& a, int j, boo
   return v;
 }
 
-// Write the four outputs of one lane at position j0 of row r.
+// ---- global-memory gather (rows longer than 8 KB, rows or outputs that are
+// not dword aligned, more than 2048 indices): plain loads and stores.
+
 template <int ES>
 __device__ __forceinline__ void store4(const GatherArgs& a, int64_t r, int j0, const uint32_t (&v)[4]) {
   uint8_t* orow = a.out + r * a.ld_out_bytes;
@@ -205,177 +216,201 @@ __device__ __forceinline__ void store4(const GatherArgs& a, int64_t r, int j0, c
   }
 }
 
-// Element at byte offset o of a row (LDS or global), 0 when o < 0.
-template <int ES, class P>
-__device__ __forceinline__ uint32_t element(P row, int32_t o) {
-  if (o < 0) return 0u;
-  if (ES == 1) return row[o];
-  return reinterpret_cast<const uint32_t*>(row)[o >> 2];
-}
-
-// Gather every output of row r from `row` (staged in LDS or in global
-// memory).  Q > 0: this lane's byte offsets are in off[Q][4]; Q == 0: the
-// indices are read (and checked) per row.
-template <int ES, int Q, class P>
-__device__ __forceinline__ void emit_row(const GatherArgs& a, P row, int64_t r, int lane,
-                                         const int32_t (&off)[Q == 0 ? 1 : Q][4], bool& bad) {
+template <int ES>
+__global__ __launch_bounds__(kGatherThreads) void gather_global_kernel(GatherArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  bool bad = false;
+  const int64_t nw = (int64_t)gridDim.x * kGatherWaves;
   const int qn = (a.k + 255) >> 8;
-  if (Q == 0) {
+  for (int64_t r = (int64_t)blockIdx.x * kGatherWaves + w; r < a.n; r += nw) {
+    const uint8_t* row = a.x + r * a.ld_bytes;
     for (int q = 0; q < qn; ++q) {
       const int j0 = 256 * q + 4 * lane;
       uint32_t v[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int32_t f = checked_index(a, j0 + e, bad);
-        v[e] = element<ES>(row, f < 0 ? -1 : f * ES);
+        v[e] = f < 0 ? 0u : (ES == 1 ? (uint32_t)row[f] : reinterpret_cast<const uint32_t*>(row)[f]);
       }
       store4<ES>(a, r, j0, v);
     }
+  }
+  if (a.status && __ballot(bad) != 0ull && lane == 0) atomicOr(a.status, 1);
+}
+
+// ---- staged gather.  Every memory operation of a unit is issued
+// unconditionally (absent lanes and rows use out-of-range buffer offsets or
+// empty buffer ranges, which access nothing), so the number of operations
+// in flight is known at compile time and waiting for one unit's loads does
+// not wait for the units behind it.
+
+// The four outputs j0 .. j0+3 of one lane for the row staged at `row`:
+// one packed store where all four are present, three single-element stores
+// for the row's last partial group (absent elements go out of range).
+template <int ES>
+__device__ __forceinline__ void emit4(__amdgpu_buffer_rsrc_t orsrc, const uint8_t* row, const int32_t (&o)[4],
+                                      int j0, int k) {
+  uint32_t v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int32_t oe = o[e] < 0 ? 0 : o[e];
+    const uint32_t x = (ES == 1) ? (uint32_t)row[oe] : *reinterpret_cast<const uint32_t*>(row + oe);
+    v[e] = o[e] < 0 ? 0u : x;
+  }
+  const bool full = j0 + 3 < k;
+  const uint32_t vo = full ? (uint32_t)(j0 * ES) : kOutOfRange;
+  if (ES == 1) {
+    __builtin_amdgcn_raw_buffer_store_b32(v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24), orsrc, (int)vo, 0,
+                                          NB_STREAM_CPOL);
   } else {
+    const dev::u32x4 q = {v[0], v[1], v[2], v[3]};
+    __builtin_amdgcn_raw_buffer_store_b128(q, orsrc, (int)vo, 0, NB_STREAM_CPOL);
+  }
 #pragma unroll
-    for (int q = 0; q < (Q == 0 ? 1 : Q); ++q) {
-      if (q < qn) {
-        uint32_t v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = element<ES>(row, off[q][e]);
-        store4<ES>(a, r, 256 * q + 4 * lane, v);
-      }
-    }
+  for (int e = 0; e < 3; ++e) {
+    const uint32_t to = (!full && j0 + e < k) ? (uint32_t)((j0 + e) * ES) : kOutOfRange;
+    if (ES == 1) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v[e], orsrc, (int)to, 0, NB_STREAM_CPOL);
+    else __builtin_amdgcn_raw_buffer_store_b32(v[e], orsrc, (int)to, 0, NB_STREAM_CPOL);
   }
 }
 
-// NL: 1 KB loads of a row per wave (0: no staging, gather from global
-// memory).  Q: 256-index groups held in registers (0: read per row).
-// A unit is RW consecutive rows; wave w takes units w, w + nw, ... and keeps
-// the loads of the next two units in flight (three register buffers) while
-// it stages and gathers the current one.
-template <int ES, int NL, int Q>
+// NL: 1 KB loads per unit; RW: rows per unit; Q: 256-index groups per lane.
+// A unit is RW consecutive rows, loaded as one contiguous span from a
+// 16-byte boundary (relative to x) with 16-byte loads; row s of unit u
+// starts at byte (u RW ld) mod 16 + s ld of the stage.  Wave w takes the
+// units w, w + nw, ... below nfast with the loads of its next two units in
+// flight (three register buffers), then the last units (whose span reaches
+// the end of the buffer) with bytewise guarded loads.
+template <int ES, int NL, int RW, int Q>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherArgs a) {
-  constexpr int RW = gather_rows<NL>();
-  constexpr int NLB = NL == 0 ? 1 : NL;
-  constexpr int QB = Q == 0 ? 1 : Q;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   bool bad = false;
 
   // byte offsets (in a row) of this lane's outputs, -1 = none
-  int32_t off[QB][4];
+  int32_t off[Q][4];
 #pragma unroll
-  for (int q = 0; q < QB; ++q)
+  for (int q = 0; q < Q; ++q)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int32_t f = (Q == 0) ? -1 : checked_index(a, 256 * q + 4 * lane + e, bad);
+      const int32_t f = checked_index(a, 256 * q + 4 * lane + e, bad);
       off[q][e] = f < 0 ? -1 : f * ES;
     }
 
   const int64_t gw = (int64_t)blockIdx.x * kGatherWaves + w;
   const int64_t nw = (int64_t)gridDim.x * kGatherWaves;
+  uint8_t* buf = lds + w * (NL * 1024);
+  const int64_t nunits = (a.n + RW - 1) / RW;
+  const int64_t mine = gw < a.nfast ? (a.nfast - 1 - gw) / nw + 1 : 0;
 
-  if (NL == 0) {
-    for (int64_t r = gw; r < a.n; r += nw) emit_row<ES, Q>(a, a.x + r * a.ld_bytes, r, lane, off, bad);
-  } else {
-    constexpr int kSlot = NLB * 1024;
-    uint8_t* buf = lds + w * (RW * kSlot);
-    const int64_t nunits = (a.n + RW - 1) / RW;
-    const int64_t mine = gw < nunits ? (nunits - 1 - gw) / nw + 1 : 0;
-    auto issue = [&](int64_t t, dev::u32x4 (&dst)[RW][NLB]) {
-      if (t < mine) {
-        const int64_t r0 = (gw + t * nw) * RW;
+  struct Unit {
+    int64_t r0, arel;
+    int32_t lead, span;
+  };
+  auto unit = [&](int64_t u) {
+    Unit v;
+    v.r0 = u * RW;
+    const int64_t rows = min((int64_t)RW, a.n - v.r0);
+    const int64_t rel = v.r0 * a.ld_bytes;
+    v.arel = rel & ~(int64_t)15;
+    v.lead = (int32_t)(rel - v.arel);
+    v.span = v.lead + (int32_t)((rows - 1) * a.ld_bytes) + a.row_bytes;
+    return v;
+  };
+  // loads of this wave's t-th fast unit (none when t >= mine)
+  auto issue = [&](int64_t t, dev::u32x4 (&dst)[NL]) {
+    const bool valid = t < mine;
+    const Unit u = unit(gw + (valid ? t : 0) * nw);
+    const auto rsrc = dev::make_rsrc(a.x + u.arel, valid ? a.total_bytes - u.arel : 0);
 #pragma unroll
-        for (int s = 0; s < RW; ++s) {
-          const int64_t r = r0 + s;
-          if (r < a.n) {
-            const int64_t base = r * a.ld_bytes;
-            const int64_t avail = a.total_bytes - base;
-            if (avail >= a.row_span) {
-              const auto rsrc = dev::make_rsrc(a.x + base, avail);
-#pragma unroll
-              for (int i = 0; i < NLB; ++i) {
-                const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
-                dst[s][i] = (p < (uint32_t)a.row_bytes) ? dev::buffer_load16(rsrc, p)
-                                                        : dev::u32x4{0u, 0u, 0u, 0u};
-              }
-            } else {  // the buffer's last row(s): bytes past its end read 0
-#pragma unroll
-              for (int i = 0; i < NLB; ++i) {
-                const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
-                dst[s][i] = (p < (uint32_t)a.row_bytes) ? dev::load16_guarded(a.x + base + p, avail - p)
-                                                        : dev::u32x4{0u, 0u, 0u, 0u};
-              }
-            }
-          }
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    };
-    auto consume = [&](int64_t t, const dev::u32x4 (&src)[RW][NLB]) {
-      const int64_t r0 = (gw + t * nw) * RW;
-      wave_lds_sync();  // the previous unit's LDS reads are done
-#pragma unroll
-      for (int s = 0; s < RW; ++s)
-#pragma unroll
-        for (int i = 0; i < NLB; ++i) {
-          const int p = (i * 64 + lane) * 16;
-          if (p < a.row_span) *reinterpret_cast<dev::u32x4*>(buf + s * kSlot + p) = src[s][i];
-        }
-      wave_lds_sync();
-#pragma unroll
-      for (int s = 0; s < RW; ++s)
-        if (r0 + s < a.n) emit_row<ES, Q>(a, buf + s * kSlot, r0 + s, lane, off, bad);
-    };
-    if (mine > 0) {
-      dev::u32x4 b0[RW][NLB], b1[RW][NLB], b2[RW][NLB];
-      issue(0, b0);
-      issue(1, b1);
-      for (int64_t t = 0;; t += 3) {
-        issue(t + 2, b2);
-        consume(t, b0);
-        if (t + 1 >= mine) break;
-        issue(t + 3, b0);
-        consume(t + 1, b1);
-        if (t + 2 >= mine) break;
-        issue(t + 4, b1);
-        consume(t + 2, b2);
-        if (t + 3 >= mine) break;
-      }
+    for (int i = 0; i < NL; ++i) {
+      const uint32_t p = (uint32_t)(i * 64 + lane) * 16u;
+      dst[i] = dev::buffer_load16(rsrc, p < (uint32_t)u.span ? p : kOutOfRange);
     }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto consume = [&](int64_t ui, const dev::u32x4 (&src)[NL]) {
+    const Unit u = unit(ui);
+    wave_lds_sync();  // the previous unit's LDS reads are done
+#pragma unroll
+    for (int i = 0; i < NL; ++i) *reinterpret_cast<dev::u32x4*>(buf + (i * 64 + lane) * 16) = src[i];
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < RW; ++s) {
+      const int64_t r = u.r0 + s;
+      const auto orsrc = dev::make_rsrc(a.out + r * a.ld_out_bytes, r < a.n ? (int64_t)a.k * ES : 0);
+      const uint8_t* row = buf + u.lead + s * (int32_t)a.ld_bytes;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) emit4<ES>(orsrc, row, off[q], 256 * q + 4 * lane, a.k);
+    }
+  };
+  if (mine > 0) {
+    dev::u32x4 b0[NL], b1[NL], b2[NL];
+    issue(0, b0);
+    issue(1, b1);
+    for (int64_t t = 0;; t += 3) {
+      issue(t + 2, b2);
+      consume(gw + t * nw, b0);
+      if (t + 1 >= mine) break;
+      issue(t + 3, b0);
+      consume(gw + (t + 1) * nw, b1);
+      if (t + 2 >= mine) break;
+      issue(t + 4, b1);
+      consume(gw + (t + 2) * nw, b2);
+      if (t + 3 >= mine) break;
+    }
+  }
+  // the last units: bytes past the end of the buffer read as 0
+  for (int64_t ui = a.nfast + gw; ui < nunits; ui += nw) {
+    const Unit u = unit(ui);
+    const int64_t avail = a.total_bytes - u.arel;
+    dev::u32x4 b[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int p = (i * 64 + lane) * 16;
+      b[i] = (p < u.span) ? dev::load16_guarded(a.x + u.arel + p, avail - p) : dev::u32x4{0u, 0u, 0u, 0u};
+    }
+    consume(ui, b);
   }
   if (a.status && __ballot(bad) != 0ull && lane == 0) atomicOr(a.status, 1);
 }
 
-template <int ES, int Q>
-const void* pick_gather_nl(int nl) {
-  switch (nl) {
-    case 1: return reinterpret_cast<const void*>(gather_kernel<ES, 1, Q>);
-    case 2: return reinterpret_cast<const void*>(gather_kernel<ES, 2, Q>);
-    case 4: return reinterpret_cast<const void*>(gather_kernel<ES, 4, Q>);
-    case 8: return reinterpret_cast<const void*>(gather_kernel<ES, 8, Q>);
-    default: return reinterpret_cast<const void*>(gather_kernel<ES, 0, Q>);
-  }
-}
-
-// Index groups held in registers for k outputs: 1, 2 or 8 (0: k > 2048).
+// Index groups held in registers for k outputs: 1, 2 or 8 (0: more than
+// 2048, gathered from global memory).
 int gather_q(int32_t k) { return k <= 256 ? 1 : (k <= 512 ? 2 : (k <= 4 * 64 * kRegQ ? 8 : 0)); }
 
-template <int ES>
-const void* pick_gather(int nl, int q) {
+template <int ES, int NL, int RW>
+const void* pick_q(int q) {
   switch (q) {
-    case 1: return pick_gather_nl<ES, 1>(nl);
-    case 2: return pick_gather_nl<ES, 2>(nl);
-    case 8: return pick_gather_nl<ES, 8>(nl);
-    default: return pick_gather_nl<ES, 0>(nl);
+    case 1: return reinterpret_cast<const void*>(gather_kernel<ES, NL, RW, 1>);
+    case 2: return reinterpret_cast<const void*>(gather_kernel<ES, NL, RW, 2>);
+    default: return reinterpret_cast<const void*>(gather_kernel<ES, NL, RW, 8>);
   }
 }
 
-int rows_per_wave(int nl) {
-  switch (nl) {
-    case 1: return gather_rows<1>();
-    case 2: return gather_rows<2>();
-    case 4: return gather_rows<4>();
-    case 8: return gather_rows<8>();
-    default: return gather_rows<0>();
+// Staged variants: (unit KB, rows per unit) = (kGatherUnitKB, 1/2/4/8) or (8, 1).
+template <int ES>
+const void* pick_gather(int nl, int rw, int q) {
+  if (nl == 8 && kGatherUnitKB != 8) return pick_q<ES, 8, 1>(q);
+  switch (rw) {
+    case 8: return pick_q<ES, kGatherUnitKB, 8>(q);
+    case 4: return pick_q<ES, kGatherUnitKB, 4>(q);
+    case 2: return pick_q<ES, kGatherUnitKB, 2>(q);
+    default: return pick_q<ES, kGatherUnitKB, 1>(q);
   }
+}
+
+// Span of unit u (rows u*rw ..) from its 16-byte boundary, rounded up to
+// whole 16-byte loads: end offset relative to x.
+int64_t unit_end(int64_t u, int64_t rw, int64_t n, int64_t ld_bytes, int64_t row_bytes) {
+  const int64_t r0 = u * rw;
+  const int64_t rows = std::min(rw, n - r0);
+  const int64_t rel = r0 * ld_bytes;
+  const int64_t arel = rel & ~(int64_t)15;
+  const int64_t span = (rel - arel) + (rows - 1) * ld_bytes + row_bytes;
+  return arel + ((span + 15) & ~(int64_t)15);
 }
 
 }  // namespace
@@ -447,23 +482,50 @@ int nb_gather_features(const void* x, int32_t xtype, int64_t n, int32_t F, int64
   a.F = F;
   a.k = k;
   a.row_bytes = F * es;
-  a.row_span = (int32_t)align_up((size_t)a.row_bytes, 16);
   a.out_vec = ((reinterpret_cast<uintptr_t>(out) & 3) == 0 && (a.ld_out_bytes & 3) == 0) ? 1 : 0;
+  a.nfast = 0;
 
-  const bool aligned = ((reinterpret_cast<uintptr_t>(x) & 3) == 0) && ((a.ld_bytes & 3) == 0);
-  int nl = 0;
-  if (aligned && a.row_span <= kMaxStagedRow) {
-    nl = 1;
-    while (nl * 1024 < a.row_span) nl *= 2;
-  }
+  // Staged when rows (plus up to 15 lead bytes) fit 8 KB, input rows and
+  // outputs are dword aligned and the indices fit in registers; units of
+  // kGatherUnitKB KB (8 KB for longer rows) holding 1, 2, 4 or 8 rows.
+  const bool aligned = ((reinterpret_cast<uintptr_t>(x) & 3) == 0) && ((a.ld_bytes & 3) == 0) && a.out_vec;
   const int q = gather_q(k);
-  const void* fn = (es == 1) ? pick_gather<1>(nl, q) : pick_gather<4>(nl, q);
-  const int rw = rows_per_wave(nl);
-  const size_t lds = nl ? (size_t)kGatherWaves * rw * nl * 1024 : 0;
-  const int64_t rows_per_wg = (int64_t)kGatherWaves * rw;
-  const int64_t need = (n + rows_per_wg - 1) / rows_per_wg;
-  const int64_t cap = (int64_t)resident_per_cu(fn, kGatherThreads, lds) * device_cu_count();
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(need, cap));
+  int nl = 0;
+  if (aligned && q > 0 && a.row_bytes + 15 <= kMaxStagedRow)
+    nl = (a.row_bytes + 15 <= kGatherUnitKB * 1024) ? kGatherUnitKB : 8;
+  const void* fn;
+  size_t lds = 0;
+  int64_t rw = 1;
+  if (nl) {
+    const int64_t pad = a.ld_bytes - a.row_bytes;
+    if (nl == kGatherUnitKB && pad * 8 <= a.ld_bytes) {
+      // the most rows whose span fits the unit
+      for (int64_t c = 8; c > 1; c /= 2)
+        if ((c - 1) * a.ld_bytes + a.row_bytes + 15 <= (int64_t)nl * 1024) {
+          rw = c;
+          break;
+        }
+    }
+    lds = (size_t)kGatherWaves * nl * 1024;
+    // no fewer units than resident waves
+    const void* f1 = (es == 1) ? pick_gather<1>(nl, (int)rw, q) : pick_gather<4>(nl, (int)rw, q);
+    const int64_t waves = (int64_t)resident_per_cu(f1, kGatherThreads, lds) * device_cu_count() * kGatherWaves;
+    while (rw > 1 && (n + rw - 1) / rw < waves) rw /= 2;
+    fn = (es == 1) ? pick_gather<1>(nl, (int)rw, q) : pick_gather<4>(nl, (int)rw, q);
+    // units whose whole rounded span lies inside the buffer (all but the last few)
+    const int64_t nunits = (n + rw - 1) / rw;
+    int64_t nf = nunits;
+    while (nf > 0 && nunits - nf < 64 && unit_end(nf - 1, rw, n, a.ld_bytes, a.row_bytes) > a.total_bytes) --nf;
+    if (nf > 0 && unit_end(nf - 1, rw, n, a.ld_bytes, a.row_bytes) > a.total_bytes) nf = 0;
+    a.nfast = nf;
+  } else {
+    fn = (es == 1) ? reinterpret_cast<const void*>(gather_global_kernel<1>)
+                   : reinterpret_cast<const void*>(gather_global_kernel<4>);
+  }
+  const int64_t cap_wg = (int64_t)resident_per_cu(fn, kGatherThreads, lds) * device_cu_count();
+  const int64_t units = (n + rw - 1) / rw;
+  const int64_t need = (units + kGatherWaves - 1) / kGatherWaves;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(need, cap_wg));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   void* args[] = {&a};
   NB_HIP_CHECK(hipLaunchKernel(fn, dim3(grid), dim3(kGatherThreads), args, lds, s));

@@ -190,6 +190,60 @@ def group_workload(g: int, n_features: int = 2000) -> Workload:
     return Workload(wid=4, n_classes=2, n_features=n_features, p_zero=0.8, clip255=True, group=g)
 
 
+# The experiment shape of the paper (sections 3-4): 13,665 executables
+# (11,305 malware, 2,360 benign) in 100 size groups of 5 KB, split 2:1 into
+# training and test files; groups 5, 8, 61, 65, 97, 98 and 100 have fewer
+# than six training files of one class.  Not given, so read here: per-group
+# file counts are lognormal(0, 1) shares of the total (at least 30 files),
+# benign files are 2,360 / 13,665 of each group's training files (at least
+# 6, and 3 in the seven groups above), and the full opcode histogram has
+# 1024 features.
+PAPER_N_GROUPS = 100
+PAPER_FILES = 13_665
+PAPER_MALWARE = 11_305
+PAPER_UNTRAINED = (4, 7, 60, 64, 96, 97, 99)     # 0-based indices of groups 5, 8, 61, 65, 97, 98, 100
+PAPER_F = 1024
+PAPER_KS = (20, 40, 80, 100, 160, 200)
+
+
+def paper_groups():
+    """(benign training files, malware training files, test-file share) per group."""
+    rng = _np_rng(6, ROLE_SIZES)
+    w = rng.lognormal(0.0, 1.0, size=PAPER_N_GROUPS)
+    sizes = np.maximum(np.rint(PAPER_FILES * w / w.sum()), 30).astype(np.int64)
+    train = np.rint(sizes * 2.0 / 3.0).astype(np.int64)
+    benign = np.maximum(np.rint(train * (1.0 - PAPER_MALWARE / PAPER_FILES)), 6).astype(np.int64)
+    malware = np.maximum(train - benign, 6).astype(np.int64)
+    benign[list(PAPER_UNTRAINED)] = 3
+    return benign, malware, sizes / sizes.sum()
+
+
+def split_files(n_total: int, share) -> np.ndarray:
+    """n_total files over groups in proportion to share (largest remainders)."""
+    share = np.asarray(share, dtype=np.float64)
+    raw = n_total * share / share.sum()
+    out = np.floor(raw).astype(np.int64)
+    rest = int(n_total - out.sum())
+    if rest > 0:
+        out[np.argsort(-(raw - out), kind="stable")[:rest]] += 1
+    return out
+
+
+def paper_group_workload(g: int, n_features: int = PAPER_F) -> Workload:
+    """Size group g of the paper-shaped experiment: its own class rates, byte
+    opcode counts with 80% zeros, test labels at the dataset's class ratio."""
+    prior = np.array([1.0 - PAPER_MALWARE / PAPER_FILES, PAPER_MALWARE / PAPER_FILES])
+    return Workload(wid=6, n_classes=2, n_features=n_features, p_zero=0.8, clip255=True, group=g, prior=prior)
+
+
+def paper_train_set(g: int, n_features: int = PAPER_F, device="cpu"):
+    """Group g's training files: its benign then its malware files."""
+    benign, malware, _ = paper_groups()
+    y = torch.cat([torch.zeros(int(benign[g]), dtype=torch.int32),
+                   torch.ones(int(malware[g]), dtype=torch.int32)]).to(device)
+    return paper_group_workload(g, n_features).features(ROLE_TRAIN_X, 0, y, device), y
+
+
 SERVE_F = (500, 1000, 5000, 500, 1000, 5000, 500, 1000)
 
 

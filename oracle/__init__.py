@@ -17,6 +17,8 @@ Modules
              occurrence difference, the feature gather, and the model trained
              on the selected features (section 3 feature selection; section 4,
              each group trained and tested on its top-k features)
+  (nb also holds the Gaussian variant: exact moment sums, mean/variance
+             with the variance floor, the density and its expanded weight form)
   precision  reduced-precision mirrors: BF16 and FP32 round-to-nearest-even
              from FP64, FP8-e4m3 quantisation of counts, certified label bands
 

@@ -14,7 +14,12 @@ Readings where the paper is silent (each listed in the design notes):
   * the multinomial coefficient is class-independent and omitted: "scores"
     are joint log-likelihoods log P(C) + sum_f x_f log theta_{C,f};
   * ties: "otherwise benign" -> the lowest class index wins an exact tie;
-  * Bernoulli presence is x > 0.
+  * Bernoulli presence is x > 0;
+  * a third variant, Gaussian NB over the occurrence counts: per class and
+    feature the mean and the (population) variance of the counts, every
+    variance increased by var_smoothing (1e-9) times the largest
+    per-feature variance of all training files together (scikit-learn's
+    GaussianNB convention, which keeps zero-variance features finite).
 
 Everything is computed in float64 straight from the definitions, with no
 blocking or fusion; large inputs are only split into row chunks.
@@ -27,6 +32,8 @@ import numpy as np
 
 MULTINOMIAL = "multinomial"
 BERNOULLI = "bernoulli"
+GAUSSIAN = "gaussian"
+VAR_SMOOTHING = 1e-9
 CHUNK_ROWS = 65536
 
 
@@ -67,6 +74,43 @@ def feature_counts(X, y, n_classes: int, kind: str = MULTINOMIAL) -> np.ndarray:
     return out
 
 
+def square_sums(X, y, n_classes: int) -> np.ndarray:
+    """Q[c, f] = sum over files of class c of x_f^2 (int64[C, F])."""
+    X = _as_np(X)
+    y = _as_np(y).astype(np.int64).reshape(-1)
+    out = np.zeros((n_classes, X.shape[1]), dtype=np.int64)
+    for c in range(n_classes):
+        for r0 in range(0, X.shape[0], CHUNK_ROWS):
+            xs = X[r0:r0 + CHUNK_ROWS][y[r0:r0 + CHUNK_ROWS] == c].astype(np.int64)
+            out[c] += (xs * xs).sum(axis=0)
+    return out
+
+
+def gaussian_moments(T, Q, Nc, var_smoothing: float = VAR_SMOOTHING):
+    """Per class and feature: mean = T / N_c and variance = (N_c Q - T^2) / N_c^2
+    (population variance; numerators in exact integers, one rounding each),
+    plus epsilon = var_smoothing * the largest variance of a feature over
+    all training files.  Returns (mean, variance + epsilon, epsilon)."""
+    T, Q, Nc = np.asarray(T), np.asarray(Q), np.asarray(Nc)
+    C, F = T.shape
+    mean = np.empty((C, F), dtype=np.float64)
+    var = np.empty((C, F), dtype=np.float64)
+    for c in range(C):
+        n = int(Nc[c])
+        for f in range(F):
+            t, q = int(T[c, f]), int(Q[c, f])
+            mean[c, f] = t / n
+            var[c, f] = (n * q - t * t) / (n * n)
+    N = int(Nc.sum())
+    top = 0.0
+    for f in range(F):
+        t = sum(int(T[c, f]) for c in range(C))
+        q = sum(int(Q[c, f]) for c in range(C))
+        top = max(top, (N * q - t * t) / (N * N))
+    eps = var_smoothing * top
+    return mean, var + eps, eps
+
+
 def log_prior(Nc) -> np.ndarray:
     """log P(C = c) = log N_c - log N, the empirical (unsmoothed) prior."""
     Nc = np.asarray(Nc, dtype=np.float64)
@@ -100,8 +144,12 @@ class Model:
     Nc: np.ndarray            # int64[C]
     counts: np.ndarray        # int64[C, F]: T (multinomial) or D (Bernoulli)
     log_prior: np.ndarray     # float64[C]
-    log_theta: np.ndarray     # float64[C, F]
+    log_theta: np.ndarray | None     # float64[C, F] (multinomial, Bernoulli)
     log_1m_theta: np.ndarray | None  # float64[C, F] (Bernoulli only)
+    sq: np.ndarray | None = None     # int64[C, F] sums of squares (Gaussian)
+    mean: np.ndarray | None = None   # float64[C, F] (Gaussian)
+    var: np.ndarray | None = None    # float64[C, F] variance + epsilon (Gaussian)
+    eps: float = 0.0                 # the variance floor added (Gaussian)
 
     @property
     def n_classes(self):
@@ -116,9 +164,14 @@ def train(X, y, n_classes: int, kind: str = MULTINOMIAL, alpha: float = 1.0) -> 
     """Fit one Naive Bayes model on labelled training files (section 4)."""
     if not alpha > 0:
         raise ValueError("alpha must be > 0")
-    if kind not in (MULTINOMIAL, BERNOULLI):
+    if kind not in (MULTINOMIAL, BERNOULLI, GAUSSIAN):
         raise ValueError(kind)
     Nc = class_totals(y, n_classes)
+    if kind == GAUSSIAN:
+        T = feature_counts(X, y, n_classes, MULTINOMIAL)
+        Q = square_sums(X, y, n_classes)
+        mean, var, eps = gaussian_moments(T, Q, Nc)
+        return Model(kind, alpha, Nc, T, log_prior(Nc), None, None, Q, mean, var, eps)
     counts = feature_counts(X, y, n_classes, kind)
     if kind == MULTINOMIAL:
         return Model(kind, alpha, Nc, counts, log_prior(Nc),
@@ -129,11 +182,18 @@ def train(X, y, n_classes: int, kind: str = MULTINOMIAL, alpha: float = 1.0) -> 
 
 def weight_form(m: Model):
     """Linear form of the scorer: s = bias + g(x) @ W.T with g(x) = x
-    (multinomial) or 1[x > 0] (Bernoulli).
+    (multinomial), 1[x > 0] (Bernoulli) or [x, x^2] (Gaussian, W = [A | B]).
 
     multinomial: W = log theta, bias = log prior
     bernoulli:   W = log theta - log(1 - theta),
-                 bias = log prior + sum_f log(1 - theta)"""
+                 bias = log prior + sum_f log(1 - theta)
+    gaussian:    A = mean / var, B = -1 / (2 var),
+                 bias = log prior - (1/2) sum_f (log(2 pi var) + mean^2 / var)"""
+    if m.kind == GAUSSIAN:
+        A = m.mean / m.var
+        B = -0.5 / m.var
+        bias = m.log_prior - 0.5 * (np.log(2.0 * np.pi * m.var) + m.mean * m.mean / m.var).sum(axis=1)
+        return np.concatenate([A, B], axis=1), bias
     if m.kind == MULTINOMIAL:
         return m.log_theta.copy(), m.log_prior.copy()
     return m.log_theta - m.log_1m_theta, m.log_prior + m.log_1m_theta.sum(axis=1)
@@ -144,7 +204,8 @@ def joint_log_likelihood(m: Model, X) -> np.ndarray:
 
     multinomial: log P(x | c) = sum_f x_f log theta[c, f]
     bernoulli:   log P(x | c) = sum_f b_f log theta + (1 - b_f) log(1 - theta),
-                 b = 1[x > 0]   (the textbook form, not the weight form)"""
+                 b = 1[x > 0]   (the textbook form, not the weight form)
+    gaussian:    log P(x | c) = -(1/2) sum_f (log(2 pi var) + (x_f - mean)^2 / var)"""
     X = _as_np(X)
     n = X.shape[0]
     if X.shape[1] != m.n_features:
@@ -156,6 +217,11 @@ def joint_log_likelihood(m: Model, X) -> np.ndarray:
             raise ValueError("occurrence counts must be non-negative")
         if m.kind == MULTINOMIAL:
             s = xs @ m.log_theta.T
+        elif m.kind == GAUSSIAN:
+            s = np.empty((xs.shape[0], m.n_classes))
+            for c in range(m.n_classes):
+                d = xs - m.mean[c][None, :]
+                s[:, c] = -0.5 * (np.log(2.0 * np.pi * m.var[c]).sum() + (d * d / m.var[c][None, :]).sum(axis=1))
         else:
             b = (xs > 0).astype(np.float64)
             s = b @ m.log_theta.T + (1.0 - b) @ m.log_1m_theta.T

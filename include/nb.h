@@ -49,6 +49,7 @@ extern "C" {
  * classical forms over occurrence counts are provided. */
 #define NB_MULTINOMIAL 0  /* P(x|c) = prod_f theta_cf^x_f (occurrences)        */
 #define NB_BERNOULLI   1  /* P(x|c) = prod_f theta_cf^b_f (1-theta_cf)^(1-b_f), b = x > 0 */
+#define NB_GAUSSIAN    2  /* P(x|c) = prod_f N(x_f; mean_cf, var_cf) over the counts */
 
 /* Feature element types. */
 #define NB_X_U8   0       /* uint8 counts (clipped at 255 by the producer)       */
@@ -97,6 +98,13 @@ typedef struct {
   size_t  off_form_bf16;    /* uint16[(P+1)*Fp] the same rows rounded to BF16   */
   size_t  off_form_bias;    /* float[P+1] biases of the scoring rows            */
   double  alpha;            /* unused by the layout; kept for ABI growth         */
+  /* Gaussian models (present in every layout, used by NB_GAUSSIAN only) */
+  size_t  off_sumsq;        /* int64[C*F]  Q_cf = sum_{i: y_i = c} x_if^2       */
+  size_t  off_mean;         /* double[C*F] mean_cf = T_cf / N_c                  */
+  size_t  off_var;          /* double[C*F] var_cf (population) + epsilon         */
+  size_t  off_form2_f32;    /* float[(P+1)*Fp] Gaussian: rows c < C hold h_cf    */
+  size_t  off_form2_bf16;   /* uint16[(P+1)*Fp] the same rows rounded to BF16    */
+  size_t  off_epsilon;      /* double[1] the variance floor epsilon              */
 } nb_layout;
 
 /* Bytes of a model buffer; 0 if C or F is out of range. */
@@ -111,20 +119,34 @@ int nb_model_layout(int32_t n_classes, int32_t n_features, nb_layout* out);
 /* ------------------------------------------------------------------ train
  * Section 4: fit one Naive Bayes model on labelled training files.
  *   N_c  = #{i : y_i = c}                                  (exact, int64)
- *   T_cf = sum_{i: y_i = c} x_if   (multinomial)           (exact, int32)
+ *   T_cf = sum_{i: y_i = c} x_if   (multinomial, Gaussian) (exact, int32)
  *   D_cf = #{i : y_i = c, x_if > 0} (Bernoulli)            (exact, int32)
+ *   Q_cf = sum_{i: y_i = c} x_if^2  (Gaussian)             (exact, int64)
  *   log prior_c = log N_c - log N   (empirical)
  *   multinomial: log theta_cf = log(T_cf + a) - log(S_c + a F)
  *   Bernoulli:   log theta_cf = log(D_cf + a) - log(N_c + 2a),
  *                log(1-theta) = log(N_c - D_cf + a) - log(N_c + 2a)
+ *   Gaussian:    mean = T / N_c, var = (N_c Q - T^2) / N_c^2 + epsilon,
+ *                epsilon = 1e-9 x the largest variance of a feature over all
+ *                training files (the variance numerators are exact
+ *                integers); the density's own form s_c = bias_c +
+ *                sum_f h_cf (x_f - mean_cf)^2 with weight h = -1 / (2 var)
+ *                and bias = log prior - (1/2) sum_f log(2 pi var); its
+ *                scoring rows are the per-class means (off_form_*) and h
+ *                (off_form2_*), rounded once, the biases b_1 - b_0 and b_0
+ *                for two classes; alpha is not used (any value > 0 is
+ *                accepted)
  * in FP64 on the device, then the FP32/BF16 scoring rows (round once).
  * x: [n x F] features (NB_X_U8 or NB_X_I32), y: int32[n] labels.
  * alpha > 0 (Laplace smoothing when 1).  min_files_per_class >= 1: a class
  * with fewer files fails with NB_EMINFILES (the paper's rule uses 6).
  * workspace: device scratch of at least nb_train_workspace_bytes(...) bytes.
  * Errors: NB_EINVAL (arguments), NB_EOVERFLOW (n*255 > INT32_MAX for bytes,
- * or a count above INT32_MAX for int32 features), NB_EDATA (label outside
- * [0, C) or negative feature), NB_EMINFILES.  Device-detected errors are
+ * or a count above INT32_MAX for int32 features; for a Gaussian model also
+ * an int32 feature of 65536 or more, whose squares could overflow the
+ * exact sums), NB_EDATA (label outside [0, C), negative feature, or a
+ * Gaussian model whose training files are all identical: every variance
+ * zero), NB_EMINFILES.  Device-detected errors are
  * reported after the stream is synchronised (the default), or by
  * nb_model_status() with NB_TRAIN_ASYNC. */
 size_t nb_train_workspace_bytes(int32_t n_classes, int32_t n_features, int64_t n, int32_t xtype);
@@ -145,7 +167,10 @@ int nb_model_status(nb_model* model, void* stream);
  * accumulation is FP32.  Outputs (device, any may be NULL but not all):
  *   labels int32[n], log_post float[n x C], scores float[n x C] (raw s_c).
  * n == 0 is a no-op.  The per-file summation order depends only on (F, C,
- * xtype, wtype), never on n or on other files. */
+ * xtype, wtype), never on n or on other files.
+ * Gaussian models: s_c = bias_c + sum_f h_cf (x_f - mean_cf)^2 (the density's
+ * own form: no large terms cancel when a variance is tiny), two classes,
+ * uint8 or int32 features, F up to 8192. */
 int nb_score(const nb_model* model, const void* x, int32_t xtype, int64_t n, int64_t ld,
              int32_t wtype, int32_t* labels, float* log_post, float* scores, void* stream);
 

@@ -12,10 +12,10 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BERNOULLI, MULTINOMIAL, NBError, TRAIN_ASYNC, W_BF16, W_F32, X_FP8, X_I32,  # noqa: F401
+from ._lib import (BERNOULLI, GAUSSIAN, MULTINOMIAL, NBError, TRAIN_ASYNC, W_BF16, W_F32, X_FP8, X_I32,  # noqa: F401
                    X_U8, check, load)
 
-KIND = {"multinomial": MULTINOMIAL, "bernoulli": BERNOULLI}
+KIND = {"multinomial": MULTINOMIAL, "bernoulli": BERNOULLI, "gaussian": GAUSSIAN}
 _XTYPE = {torch.uint8: X_U8, torch.int32: X_I32, torch.float8_e4m3fn: X_FP8}
 
 
@@ -103,6 +103,30 @@ class Model:
 
     def form_bias(self):
         return self._view(self.layout.off_form_bias, torch.float32, self.layout.form_rows + 1)
+
+    # Gaussian models
+    def sumsq(self):
+        C, F = self.n_classes, self.n_features
+        return self._view(self.layout.off_sumsq, torch.int64, C * F).view(C, F)
+
+    def mean(self):
+        C, F = self.n_classes, self.n_features
+        return self._view(self.layout.off_mean, torch.float64, C * F).view(C, F)
+
+    def var(self):
+        C, F = self.n_classes, self.n_features
+        return self._view(self.layout.off_var, torch.float64, C * F).view(C, F)
+
+    def form2_f32(self):
+        P, Fp = self.layout.form_rows, self.layout.padded_features
+        return self._view(self.layout.off_form2_f32, torch.float32, (P + 1) * Fp).view(P + 1, Fp)
+
+    def form2_bf16(self):
+        P, Fp = self.layout.form_rows, self.layout.padded_features
+        return self._view(self.layout.off_form2_bf16, torch.int16, (P + 1) * Fp).view(P + 1, Fp)
+
+    def epsilon(self):
+        return self._view(self.layout.off_epsilon, torch.float64, 1)
 
 
 def train_workspace(model: Model, n: int, xtype: int = X_U8, device="cuda"):

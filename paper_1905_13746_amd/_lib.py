@@ -16,7 +16,7 @@ STATUS_NAMES = {
     -5: "NB_EDATA", -6: "NB_ENOMEM", -7: "NB_EHIP", -8: "NB_EREJECTED",
 }
 
-MULTINOMIAL, BERNOULLI = 0, 1
+MULTINOMIAL, BERNOULLI, GAUSSIAN = 0, 1, 2
 X_U8, X_I32, X_FP8 = 0, 1, 2
 W_F32, W_BF16 = 0, 1
 TRAIN_ASYNC = 1
@@ -38,7 +38,10 @@ class NbLayout(ctypes.Structure):
                 ("off_log_theta", ctypes.c_size_t), ("off_log_1m_theta", ctypes.c_size_t),
                 ("off_weight", ctypes.c_size_t), ("off_bias", ctypes.c_size_t),
                 ("off_form_f32", ctypes.c_size_t), ("off_form_bf16", ctypes.c_size_t),
-                ("off_form_bias", ctypes.c_size_t), ("alpha", ctypes.c_double)]
+                ("off_form_bias", ctypes.c_size_t), ("alpha", ctypes.c_double),
+                ("off_sumsq", ctypes.c_size_t), ("off_mean", ctypes.c_size_t), ("off_var", ctypes.c_size_t),
+                ("off_form2_f32", ctypes.c_size_t),
+                ("off_form2_bf16", ctypes.c_size_t), ("off_epsilon", ctypes.c_size_t)]
 
 
 class NbGroup(ctypes.Structure):

@@ -60,6 +60,12 @@ bool compute_layout(int32_t C, int32_t F, nb_layout* L) {
   L->off_form_f32 = take(4 * (P + 1) * Fp);
   L->off_form_bf16 = take(2 * (P + 1) * Fp);
   L->off_form_bias = take(4 * (P + 1));
+  L->off_sumsq = take(8 * CF);
+  L->off_mean = take(8 * CF);
+  L->off_var = take(8 * CF);
+  L->off_form2_f32 = take(4 * (P + 1) * Fp);
+  L->off_form2_bf16 = take(2 * (P + 1) * Fp);
+  L->off_epsilon = take(8);
   L->total_bytes = off;
   return true;
 }
@@ -69,8 +75,8 @@ int check_model(const nb_model* m, nb_layout* L) {
   if (!m->dev) return fail(NB_EINVAL, "model->dev is NULL");
   if ((reinterpret_cast<uintptr_t>(m->dev) & (kAlign - 1)) != 0)
     return fail(NB_EINVAL, "model->dev must be 256-byte aligned");
-  if (m->kind != NB_MULTINOMIAL && m->kind != NB_BERNOULLI)
-    return fail(NB_EINVAL, "model->kind must be NB_MULTINOMIAL or NB_BERNOULLI");
+  if (m->kind != NB_MULTINOMIAL && m->kind != NB_BERNOULLI && m->kind != NB_GAUSSIAN)
+    return fail(NB_EINVAL, "model->kind must be NB_MULTINOMIAL, NB_BERNOULLI or NB_GAUSSIAN");
   if (!compute_layout(m->n_classes, m->n_features, L))
     return fail(NB_EINVAL, "model class/feature count out of range (C in [2,256], F in [1,2^20])");
   return NB_OK;

@@ -394,6 +394,8 @@ int setup_groups(const nb_model* models, int32_t n_models, const nb_group* group
     const nb_model* m = &models[groups[route[g]].model];
     if (m->n_classes != 2)
       return fail(NB_EINVAL, "group scoring takes two-class models (benign / malware per size group)");
+    if (m->kind == NB_GAUSSIAN)
+      return fail(NB_EINVAL, "group scoring takes multinomial and Bernoulli models (Gaussian models: nb_score)");
     if (m->n_features != S->F || (m->kind == NB_BERNOULLI) != S->bin)
       return fail(NB_EINVAL, "all group models must share the kind and the feature count");
     if (G.n < 0) return fail(NB_EINVAL, "group " + std::to_string(g) + ": n must be >= 0");

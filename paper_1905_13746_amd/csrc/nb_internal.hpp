@@ -39,6 +39,7 @@ enum StatusFlag : int32_t {
   kFlagOverflow = 4,      // count above INT32_MAX
   kFlagMinFiles = 8,      // class below the minimum number of files
   kFlagBadIndex = 16,     // feature index outside [0, F) (nb_model_select)
+  kFlagZeroVariance = 32, // Gaussian: every training file identical (all variances 0)
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

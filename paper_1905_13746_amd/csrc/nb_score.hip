@@ -31,18 +31,19 @@
 namespace nb {
 namespace {
 
-template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false>
 __global__ __launch_bounds__(kThreads) void score2_kernel(Score2Args a) {
-  extern __shared__ float tbl[];        // [NS][Fp]
+  extern __shared__ float tbl[];        // [NS][Fp] (Gaussian: [4][Fp], means then h)
   __shared__ float stage[kWaves][NS][(64 / LPR) * kRowSteps];
-  stage_table<NS>(a, tbl);
+  if constexpr (QUAD) stage_table_q(a, tbl);
+  else stage_table<NS>(a, tbl);
   __syncthreads();
   constexpr int BR = (64 / LPR) * kRowSteps;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wave_id = (int64_t)blockIdx.x * kWaves + wave;
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
   const int64_t nblk = (a.n + BR - 1) / BR;
-  score_blocks<XT, LPR, NS, BIN, MULTI>(a, tbl, wave_id, nwaves, nblk, stage);
+  score_blocks<XT, LPR, NS, BIN, MULTI, QUAD>(a, tbl, wave_id, nwaves, nblk, stage);
 }
 
 struct Single {
@@ -52,15 +53,36 @@ struct Single {
   }
 };
 
+// Gaussian two-class kernels (uint8 and int32 features).
+template <int XT, int NS>
+const void* pick_quad_lpr(int lpr, bool multi) {
+  switch (lpr) {
+    case 4: return reinterpret_cast<const void*>(score2_kernel<XT, 4, NS, false, false, true>);
+    case 8: return reinterpret_cast<const void*>(score2_kernel<XT, 8, NS, false, false, true>);
+    case 16: return reinterpret_cast<const void*>(score2_kernel<XT, 16, NS, false, false, true>);
+    case 32: return reinterpret_cast<const void*>(score2_kernel<XT, 32, NS, false, false, true>);
+    default:
+      return multi ? reinterpret_cast<const void*>(score2_kernel<XT, 64, NS, false, true, true>)
+                   : reinterpret_cast<const void*>(score2_kernel<XT, 64, NS, false, false, true>);
+  }
+}
+
+const void* pick_quad(int xtype, int lpr, bool multi, int ns) {
+  if (xtype == NB_X_I32) return ns == 1 ? pick_quad_lpr<NB_X_I32, 1>(lpr, multi) : pick_quad_lpr<NB_X_I32, 2>(lpr, multi);
+  return ns == 1 ? pick_quad_lpr<NB_X_U8, 1>(lpr, multi) : pick_quad_lpr<NB_X_U8, 2>(lpr, multi);
+}
+
 int launch_score2(const nb_model* m, const nb_layout& L, const void* x, int32_t xtype, int64_t n, int64_t ld,
                   int32_t wtype, int32_t* labels, float* log_post, float* scores, hipStream_t s) {
   const int ns = scores ? 2 : 1;
+  const bool quad = (m->kind == NB_GAUSSIAN);
   Score2Args a;
-  const int rc = make_score2_args(m, L, x, xtype, n, ld, wtype, labels, log_post, scores, ns, &a);
+  const int rc = make_score2_args(m, L, x, xtype, n, ld, wtype, labels, log_post, scores, ns, &a, quad);
   if (rc) return rc;
   const int lpr = lanes_per_row(a.F);
-  const size_t lds = (size_t)ns * a.Fp * sizeof(float);
-  const void* fn = pick_score2<Single>(xtype, lpr, a.nch > 1, ns, m->kind == NB_BERNOULLI);
+  const size_t lds = (size_t)(quad ? 4 : ns) * a.Fp * sizeof(float);
+  const void* fn = quad ? pick_quad(xtype, lpr, a.nch > 1, ns)
+                        : pick_score2<Single>(xtype, lpr, a.nch > 1, ns, m->kind == NB_BERNOULLI);
   if (lds > 64 * 1024) NB_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   const int64_t rows_per_blk = (int64_t)(64 / lpr) * kRowSteps;
   const int64_t nblk = (n + rows_per_blk - 1) / rows_per_blk;
@@ -104,6 +126,8 @@ extern "C" int nb_score(const nb_model* m, const void* x, int32_t xtype, int64_t
   int rc = check_score_args(m, &L, x, xtype, n, ld, wtype, labels, log_post, scores);
   if (rc || n == 0) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (m->kind == NB_GAUSSIAN && (m->n_classes != 2 || xtype == NB_X_FP8))
+    return fail(NB_EINVAL, "Gaussian models score two classes with uint8 or int32 features");
   if (m->n_classes == 2) return launch_score2(m, L, x, xtype, n, ld, wtype, labels, log_post, scores, s);
   // BF16 tables with a full column tile of classes go to the matrix cores;
   // everything else (the FP32 plain path, fewer classes, int32 features) to

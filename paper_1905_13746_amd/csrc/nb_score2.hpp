@@ -39,6 +39,8 @@ struct Score2Args {
   int64_t total_bytes;
   const float* rows32;      // [2][Fp] log-odds row, aux row
   const uint16_t* rows16;   // same rows in BF16
+  const float* rows32_q;    // Gaussian: [2][Fp] rows of the x^2 weights
+  const uint16_t* rows16_q; //   (log-odds, aux), FP32 / BF16
   const float* row_bias;    // [2]
   int32_t* labels;
   float* log_post;
@@ -228,12 +230,67 @@ __device__ __forceinline__ void accumulate_rows(dev::u32x4 (&v)[kRowSteps][NV], 
 }
 
 
+// Gaussian models: s_c = b_c + sum_f h_cf (x_f - mean_cf)^2 (the density's
+// own form).  Two classes: the LDS table holds four rows, mean_0, mean_1,
+// h_0, h_1; acc[0] gathers the log-odds terms h_1 d_1^2 - h_0 d_0^2 and,
+// with raw scores, acc[1] the terms h_0 d_0^2 of s_0, so the reduction and
+// the epilogue are those of the linear kinds.
+template <int XT>
+__device__ __forceinline__ void load_table_q(const float* tbl, int Fp, int fc, float (&mu)[2][16],
+                                             float (&h)[2][16]) {
+  load_table<XT, 2>(tbl, Fp, fc, mu);
+  load_table<XT, 2>(tbl + 2 * Fp, Fp, fc, h);
+}
+
+template <int XT, int NS>
+__device__ __forceinline__ void accumulate_seg_q(const dev::u32x4 (&v)[(XT == NB_X_I32) ? 4 : 1],
+                                                 const float (&mu)[2][16], const float (&h)[2][16],
+                                                 float (&acc)[NS]) {
+  float xf[16];
+  if (XT == NB_X_I32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) xf[4 * q + d] = (float)(int32_t)v[q][d];
+  } else {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t u = v[0][d];
+      xf[4 * d + 0] = (float)(u & 0xFFu);
+      xf[4 * d + 1] = (float)((u >> 8) & 0xFFu);
+      xf[4 * d + 2] = (float)((u >> 16) & 0xFFu);
+      xf[4 * d + 3] = (float)(u >> 24);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const float d0 = xf[e] - mu[0][e], d1 = xf[e] - mu[1][e];
+    const float t0 = h[0][e] * d0, t1 = h[1][e] * d1;
+    acc[0] = fmaf(t1, d1, fmaf(-t0, d0, acc[0]));
+    if (NS == 2) acc[NS - 1] = fmaf(t0, d0, acc[NS - 1]);
+  }
+}
+
+template <int XT, int NS, int NV>
+__device__ __forceinline__ void accumulate_rows_q(dev::u32x4 (&v)[kRowSteps][NV], const float (&mu)[2][16],
+                                                  const float (&h)[2][16], float (&acc)[kRowSteps][NS]) {
+#pragma unroll
+  for (int i = 0; i < kRowSteps; ++i) accumulate_seg_q<XT, NS>(v[i], mu, h, acc[i]);
+}
+
 // Copy the NS scoring rows (FP32, or BF16 widened: exact) into LDS.  The
 // caller synchronises the workgroup afterwards.
 template <int NS>
 __device__ __forceinline__ void stage_table(const Score2Args& a, float* tbl) {
   for (int i = threadIdx.x; i < NS * a.Fp; i += kThreads)
     tbl[i] = (a.wt == NB_W_BF16) ? dev::bf16_to_f32(a.rows16[i]) : a.rows32[i];
+}
+
+// Gaussian (two classes): the two mean rows, then the two h rows.
+__device__ __forceinline__ void stage_table_q(const Score2Args& a, float* tbl) {
+  stage_table<2>(a, tbl);
+  for (int i = threadIdx.x; i < 2 * a.Fp; i += kThreads)
+    tbl[2 * a.Fp + i] = (a.wt == NB_W_BF16) ? dev::bf16_to_f32(a.rows16_q[i]) : a.rows32_q[i];
 }
 
 // One wave scores the blocks first, first + stride, ... below `end` of the
@@ -243,7 +300,8 @@ __device__ __forceinline__ void stage_table(const Score2Args& a, float* tbl) {
 // of the next unit (block, chunk) in flight while the current one is
 // accumulated.  The rest take guarded loads.  tbl: the rows in LDS.
 // MULTI: F spans more than one chunk of 16*LPR features (only with LPR = 64).
-template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+// QUAD: a Gaussian model (x and x^2 rows, see accumulate_seg_q).
+template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false>
 __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* tbl, int64_t first, int64_t stride,
                                              int64_t end, float (*stage)[NS][(64 / LPR) * kRowSteps]) {
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
@@ -267,10 +325,15 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
 #pragma unroll
   for (int s = 0; s < NS; ++s) rb[s] = a.row_bias[s];
 
-  float w[NS][16];
+  float w[QUAD ? 2 : NS][16];        // Gaussian: the means
+  float w2[QUAD ? 2 : 1][16];        // Gaussian: h
   uint32_t keep[4] = {~0u, ~0u, ~0u, ~0u};
+  auto load_w = [&](int fc) {
+    if constexpr (QUAD) load_table_q<XT>(tbl, a.Fp, fc, w, w2);
+    else load_table<XT, NS>(tbl, a.Fp, fc, w);
+  };
   if (!MULTI) {
-    load_table<XT, NS>(tbl, a.Fp, 16 * j, w);
+    load_w(16 * j);
     if (XT == NB_X_FP8) fp8_keep_mask(a.F, 16 * j, keep);
   }
 
@@ -279,6 +342,10 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
   for (int i = 0; i < R; ++i)
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+  auto accumulate = [&](dev::u32x4 (&v)[R][NV]) {
+    if constexpr (QUAD) accumulate_rows_q<XT, NS, NV>(v, w, w2, acc);
+    else accumulate_rows<XT, NS, BIN, NV>(v, w, keep, true, acc);
+  };
 
   // ---- fast blocks: first + i*stride < min(end, nfast).  Per-wave counters
   // are 32-bit so loop control stays on the scalar unit.
@@ -317,10 +384,10 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
   auto consume = [&](dev::u32x4 (&src)[R][NV]) {
     if (MULTI) {
       const int fc = cch * CW + 16 * j;
-      load_table<XT, NS>(tbl, a.Fp, fc, w);
+      load_w(fc);
       if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
     }
-    accumulate_rows<XT, NS, BIN, NV>(src, w, keep, true, acc);
+    accumulate(src);
     if (++cch == nch) {
       finish_block<LPR, NS, true>(a, acc, lane, wave, sub, rb, (first + (int64_t)cb * stride) * BR, BR, stage);
 #pragma unroll
@@ -360,7 +427,7 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
     for (int ch = 0; ch < nch; ++ch) {
       const int fc = ch * CW + 16 * j;
       if (MULTI) {
-        load_table<XT, NS>(tbl, a.Fp, fc, w);
+        load_w(fc);
         if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
       }
       dev::u32x4 v[R][NV];
@@ -376,7 +443,7 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
             v[i][q] = dev::load16_guarded(a.x + off + 16 * q, a.total_bytes - off - 16 * q);
         }
       }
-      accumulate_rows<XT, NS, BIN, NV>(v, w, keep, true, acc);
+      accumulate(v);
     }
     finish_block<LPR, NS, false>(a, acc, lane, wave, sub, rb, row0, nrows, stage);
 #pragma unroll
@@ -399,14 +466,16 @@ constexpr size_t kMaxTableLds = 128 * 1024;
 // Launch arguments of the two-class kernels for one model and one feature
 // matrix (arguments already validated).  Returns NB_OK or NB_EINVAL.
 int make_score2_args(const nb_model* m, const nb_layout& L, const void* x, int32_t xtype, int64_t n, int64_t ld,
-                     int32_t wtype, int32_t* labels, float* log_post, float* scores, int ns, Score2Args* out) {
+                     int32_t wtype, int32_t* labels, float* log_post, float* scores, int ns, Score2Args* out,
+                     bool quad = false) {
   const int F = m->n_features;
   const int eb = elem_bytes(xtype);
   const int lpr = lanes_per_row(F);
   const int cw = 16 * lpr;
   const int nch = (F + cw - 1) / cw;
-  if ((size_t)ns * L.padded_features * sizeof(float) > kMaxTableLds)
-    return fail(NB_EINVAL, "two-class scoring supports F up to 16384 (table staged in LDS)");
+  if ((size_t)(quad ? 4 : ns) * L.padded_features * sizeof(float) > kMaxTableLds)
+    return fail(NB_EINVAL, quad ? "two-class Gaussian scoring supports F up to 8192 (tables staged in LDS)"
+                                : "two-class scoring supports F up to 16384 (table staged in LDS)");
   const uint8_t* base = static_cast<const uint8_t*>(m->dev);
   Score2Args a;
   a.x = static_cast<const uint8_t*>(x);
@@ -416,6 +485,8 @@ int make_score2_args(const nb_model* m, const nb_layout& L, const void* x, int32
   a.rows32 = reinterpret_cast<const float*>(base + L.off_form_f32);
   a.rows16 = reinterpret_cast<const uint16_t*>(base + L.off_form_bf16);
   a.row_bias = reinterpret_cast<const float*>(base + L.off_form_bias);
+  a.rows32_q = reinterpret_cast<const float*>(base + L.off_form2_f32);
+  a.rows16_q = reinterpret_cast<const uint16_t*>(base + L.off_form2_bf16);
   a.labels = labels;
   a.log_post = log_post;
   a.scores = scores;

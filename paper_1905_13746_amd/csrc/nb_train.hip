@@ -61,7 +61,11 @@ struct CountArgs {
   int32_t F, C, Fp;
 };
 
-template <int XT, bool BIN>
+// SQ: sums of squares x^2 instead of counts (the Gaussian variant's second
+// moment): 32-bit per-feature lane sums for byte features (flushed to int64
+// before they can wrap), int64 for int32 features (values of 65536 or more
+// are flagged: their squares could overflow the exact int64 sums).
+template <int XT, bool BIN, bool SQ = false>
 __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;   // bytes per feature
   constexpr int NV = EB;                          // 16-byte vectors per lane per row
@@ -84,22 +88,33 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
 
   // byte features: packed 16-bit lanes (lo: bytes 0,2; hi: bytes 1,3 of each dword)
   uint32_t lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+  uint32_t sq32[SQ ? kSeg : 1];
+#pragma unroll
+  for (int e = 0; e < (SQ ? kSeg : 1); ++e) sq32[e] = 0;
   int64_t acc[kSeg];
 #pragma unroll
   for (int e = 0; e < kSeg; ++e) acc[e] = 0;
   int packed_rows = 0;
   int64_t matched = 0;
-  bool bad_label = false, negative = false;
+  bool bad_label = false, negative = false, too_large = false;
 
   auto flush = [&]() {
+    if (SQ) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      acc[4 * k + 0] += lo[k] & 0xFFFFu;
-      acc[4 * k + 2] += lo[k] >> 16;
-      acc[4 * k + 1] += hi[k] & 0xFFFFu;
-      acc[4 * k + 3] += hi[k] >> 16;
-      lo[k] = 0;
-      hi[k] = 0;
+      for (int e = 0; e < (SQ ? kSeg : 1); ++e) {
+        acc[e] += sq32[e];
+        sq32[e] = 0;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc[4 * k + 0] += lo[k] & 0xFFFFu;
+        acc[4 * k + 2] += lo[k] >> 16;
+        acc[4 * k + 1] += hi[k] & 0xFFFFu;
+        acc[4 * k + 3] += hi[k] >> 16;
+        lo[k] = 0;
+        hi[k] = 0;
+      }
     }
     packed_rows = 0;
   };
@@ -176,7 +191,18 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
               const int32_t val = (int32_t)v[k][q][d];
               const bool valid = (f0 + e) < a.F;
               if (valid && val < 0) negative = true;
-              if (valid) acc[e] += BIN ? (int64_t)(val > 0) : (int64_t)val;
+              if (SQ && valid && val >= 65536) too_large = true;
+              if (valid) acc[e] += SQ ? (int64_t)val * val : (BIN ? (int64_t)(val > 0) : (int64_t)val);
+            }
+          }
+        } else if (SQ) {
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const uint32_t w = v[k][0][d];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const uint32_t x = (w >> (8 * b)) & 0xFFu;
+              sq32[(4 * d + b) % (SQ ? kSeg : 1)] += x * x;
             }
           }
         } else {
@@ -194,8 +220,9 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
         }
       }
       if (XT != NB_X_I32) {
+        // packed 16-bit counts hold 256 rows; 32-bit square sums 66,051
         packed_rows += cnt;
-        if (packed_rows > 256 - kBatch) flush();
+        if (packed_rows > (SQ ? 65536 : 256) - kBatch) flush();
       }
     }
   }
@@ -204,9 +231,10 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   {
     const int any_bad = __syncthreads_or(bad_label && cls == 0 && ch == 0);
     const int any_neg = __syncthreads_or(negative);
+    const int any_big = __syncthreads_or(too_large);
     if (threadIdx.x == 0)
       a.flag_part[((int64_t)slot * a.C + cls) * gridDim.z + ch] =
-          (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0);
+          (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0) | (any_big ? kFlagOverflow : 0);
   }
 
   // combine the four waves in LDS, then one partial row per workgroup
@@ -341,7 +369,7 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
   // the count kernel's flags (every class workgroup gathers all of them)
   int32_t fl = 0;
   for (int i = t; i < a.n_flags; i += 256) fl |= a.flag_part[i];
-  const int any_over = __syncthreads_or(over);
+  const int any_over = __syncthreads_or(over || (fl & kFlagOverflow));
   const int any_bad = __syncthreads_or(fl & kFlagBadLabel);
   const int any_neg = __syncthreads_or(fl & kFlagNegative);
   const int any_idx = __syncthreads_or(fl & kFlagBadIndex);
@@ -363,12 +391,13 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
   const int64_t Nc = snc[c];
   if (t == 0) {
     a.class_totals[c] = Nc;
-    a.class_sums[c] = (a.kind == NB_MULTINOMIAL) ? Sc : Nc;
+    a.class_sums[c] = (a.kind == NB_BERNOULLI) ? Nc : Sc;
     a.class_flags[c] = (any_over ? kFlagOverflow : 0) | ((Nc < a.min_files || Nc < 1) ? kFlagMinFiles : 0) |
                        (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0) |
                        (any_idx ? kFlagBadIndex : 0);
   }
 
+  if (a.kind == NB_GAUSSIAN) return;   // its tables follow from the moments (gauss_tables)
   const double al = a.alpha;
   double part = 0.0;
   if (a.kind == NB_MULTINOMIAL) {
@@ -433,7 +462,7 @@ __global__ __launch_bounds__(256) void form_rows(const double* __restrict__ W, c
       rows16[(int64_t)C * Fp + f] = dev::f64_to_bf16_rne(m);
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && row_bias) {
     if (C == 2) {
       row_bias[0] = (float)(bias[1] - bias[0]);
       row_bias[1] = (float)bias[0];
@@ -443,6 +472,139 @@ __global__ __launch_bounds__(256) void form_rows(const double* __restrict__ W, c
       mb /= (double)C;
       for (int c = 0; c < C; ++c) row_bias[c] = (float)(bias[c] - mb);
       row_bias[C] = (float)mb;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && status) {
+    int32_t flags = 0;
+    for (int c = 0; c < C; ++c) flags |= class_flags[c];
+    status[kStatusFlags] = flags;
+    status[kStatusTrained] = (flags == 0) ? 1 : 0;
+    status[2] = 0;
+    status[3] = 0;
+  }
+}
+
+// ------------------------------------------------------------ Gaussian
+typedef unsigned __int128 u128;
+
+// Nonnegative 128-bit integer to FP64 (at most two roundings).
+__device__ __forceinline__ double u128_to_double(u128 v) {
+  return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
+}
+
+// n^2 times the population variance of n values with sum t and sum of
+// squares q: n q - t^2 (>= 0), exact.
+__device__ __forceinline__ u128 var_numerator(int64_t n, int64_t t, int64_t q) {
+  return (u128)(uint64_t)n * (uint64_t)q - (u128)(uint64_t)t * (uint64_t)t;
+}
+
+// Q_cf: the last level of the square sums.  grid (ceil(F/256), C).
+__global__ __launch_bounds__(256) void sumsq_finish(const int64_t* __restrict__ part2_sq, int RS, int C, int F,
+                                                   int Fp, int64_t* __restrict__ sumsq) {
+  const int c = blockIdx.y, f = blockIdx.x * 256 + threadIdx.x;
+  if (f < F) {
+    int64_t v[kReduceSplit];
+#pragma unroll
+    for (int r = 0; r < kReduceSplit; ++r) v[r] = (r < RS) ? part2_sq[((int64_t)r * C + c) * Fp + f] : 0;
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kReduceSplit; ++r) s += v[r];
+    sumsq[(int64_t)c * F + f] = s;
+  }
+}
+
+// epsilon = 1e-9 x the largest variance of a feature over all training
+// files (classes pooled).  One workgroup.
+__global__ __launch_bounds__(256) void gauss_eps(const int32_t* __restrict__ counts,
+                                                const int64_t* __restrict__ sumsq,
+                                                const int64_t* __restrict__ class_totals, int C, int F,
+                                                double* __restrict__ eps_out, int32_t* __restrict__ class_flags) {
+  const int t = threadIdx.x;
+  int64_t N = 0;
+  for (int c = 0; c < C; ++c) N += class_totals[c];
+  double m = 0.0;
+  for (int f = t; f < F; f += 256) {
+    int64_t tf = 0, qf = 0;
+    for (int c = 0; c < C; ++c) {
+      tf += counts[(int64_t)c * F + f];
+      qf += sumsq[(int64_t)c * F + f];
+    }
+    const double v = u128_to_double(var_numerator(N, tf, qf)) / (double)N / (double)N;
+    m = fmax(m, v);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  __shared__ double red[4];
+  if ((t & 63) == 0) red[t >> 6] = m;
+  __syncthreads();
+  if (t == 0) {
+    const double top = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    *eps_out = 1e-9 * top;
+    if (!(top > 0.0)) class_flags[0] |= kFlagZeroVariance;
+  }
+}
+
+// Per class: mean, variance + epsilon, the weight h = -1 / (2 var) and the
+// bias log prior - (1/2) sum_f log(2 pi var) (fixed-order reduction) of the
+// score form s = bias + sum_f h (x - mean)^2.  grid C.
+__global__ __launch_bounds__(256) void gauss_tables(const int32_t* __restrict__ counts,
+                                                   const int64_t* __restrict__ sumsq,
+                                                   const int64_t* __restrict__ class_totals,
+                                                   const double* __restrict__ eps_in, int C, int F,
+                                                   double* __restrict__ mean, double* __restrict__ var,
+                                                   double* __restrict__ weight, double* __restrict__ bias) {
+  const int c = blockIdx.x, t = threadIdx.x;
+  const double eps = *eps_in;
+  const int64_t Nc = class_totals[c];
+  int64_t N = 0;
+  for (int k = 0; k < C; ++k) N += class_totals[k];
+  const double dn = (double)Nc;
+  double part = 0.0;
+  for (int f = t; f < F; f += 256) {
+    const int64_t i = (int64_t)c * F + f;
+    const int64_t tf = counts[i], qf = sumsq[i];
+    const double mu = (double)tf / dn;
+    const double v = u128_to_double(var_numerator(Nc, tf, qf)) / dn / dn + eps;
+    mean[i] = mu;
+    var[i] = v;
+    weight[i] = -0.5 / v;
+    part += log(2.0 * M_PI * v);
+  }
+  __shared__ double red_d[4];
+  const double s = block_sum<double>(part, red_d);
+  if (t == 0) bias[c] = log(dn) - log((double)N) - 0.5 * s;
+}
+
+// Gaussian scoring rows: row c of the first set is mean_c, row c of the
+// second is h_c, each rounded once to FP32 and to BF16, zero padded; the
+// row biases are b_1 - b_0 and b_0 for two classes (b_c otherwise); then
+// the status word.  grid Fp / 256.
+__global__ __launch_bounds__(256) void gauss_rows(const double* __restrict__ mean, const double* __restrict__ h,
+                                                 const double* __restrict__ bias, int C, int F, int Fp,
+                                                 float* __restrict__ mu32, uint16_t* __restrict__ mu16,
+                                                 float* __restrict__ h32, uint16_t* __restrict__ h16,
+                                                 float* __restrict__ row_bias,
+                                                 const int32_t* __restrict__ class_flags,
+                                                 int32_t* __restrict__ status) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f < Fp) {
+    for (int c = 0; c < C; ++c) {
+      const int64_t o = (int64_t)c * Fp + f;
+      const double m = (f < F) ? mean[(int64_t)c * F + f] : 0.0;
+      const double w = (f < F) ? h[(int64_t)c * F + f] : 0.0;
+      mu32[o] = (float)m;
+      mu16[o] = dev::f64_to_bf16_rne(m);
+      h32[o] = (float)w;
+      h16[o] = dev::f64_to_bf16_rne(w);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (C == 2) {
+      row_bias[0] = (float)(bias[1] - bias[0]);
+      row_bias[1] = (float)bias[0];
+    } else {
+      for (int c = 0; c < C; ++c) row_bias[c] = (float)bias[c];
+      row_bias[C] = 0.0f;
     }
     int32_t flags = 0;
     for (int c = 0; c < C; ++c) flags |= class_flags[c];
@@ -475,7 +637,7 @@ int64_t train_slots(int32_t C, int32_t F, int64_t n, int32_t xtype) {
 // second-level partials of each.
 struct TrainWs {
   int64_t S, RS;
-  size_t off_part, off_nc, off_part2, off_nc2, off_flags, total;
+  size_t off_part, off_nc, off_part2, off_nc2, off_part_sq, off_part2_sq, off_flags, total;
 };
 
 TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
@@ -492,8 +654,12 @@ TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
   w.off_nc = take((size_t)S * C * 8);
   w.off_part2 = take((size_t)w.RS * C * Fp * 8);
   w.off_nc2 = take((size_t)w.RS * C * 8);
-  // count-kernel flags [S][C][chunks], then per-class flags
-  w.off_flags = take(((size_t)S * C * (Fp / kChunk) + C) * 4);
+  // square sums of a Gaussian model (the workspace size does not depend on
+  // the kind)
+  w.off_part_sq = take((size_t)S * C * Fp * 8);
+  w.off_part2_sq = take((size_t)w.RS * C * Fp * 8);
+  // count-kernel flags [2][S][C][chunks] (counts, squares), then per-class flags
+  w.off_flags = take(((size_t)2 * S * C * (Fp / kChunk) + C) * 4);
   w.total = off;
   return w;
 }
@@ -550,7 +716,7 @@ SelectWs select_ws(int32_t C, int32_t k, int32_t Fp) {
 // second-level partials, then the scoring rows and the status word.
 int launch_tables(nb_model* m, const nb_layout& L, const int64_t* part2, const int64_t* nc2, int RS,
                   const int32_t* flag_part, int n_flags, int32_t* class_flags, double alpha, int min_files,
-                  hipStream_t s) {
+                  hipStream_t s, const int64_t* part2_sq = nullptr) {
   uint8_t* base = static_cast<uint8_t*>(m->dev);
   TableArgs ta;
   ta.part2 = part2;
@@ -574,6 +740,29 @@ int launch_tables(nb_model* m, const nb_layout& L, const int64_t* part2, const i
   ta.min_files = min_files;
   hipLaunchKernelGGL(class_tables, dim3((unsigned)ta.C), dim3(256), 0, s, ta);
   NB_HIP_CHECK(hipGetLastError());
+  if (m->kind == NB_GAUSSIAN) {
+    int64_t* sumsq = reinterpret_cast<int64_t*>(base + L.off_sumsq);
+    double* eps = reinterpret_cast<double*>(base + L.off_epsilon);
+    hipLaunchKernelGGL(sumsq_finish, dim3((unsigned)((ta.F + 255) / 256), (unsigned)ta.C), dim3(256), 0, s,
+                       part2_sq, RS, ta.C, ta.F, ta.Fp, sumsq);
+    NB_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(gauss_eps, dim3(1), dim3(256), 0, s, ta.counts, sumsq, ta.class_totals, ta.C, ta.F, eps,
+                       class_flags);
+    NB_HIP_CHECK(hipGetLastError());
+    double* mean = reinterpret_cast<double*>(base + L.off_mean);
+    hipLaunchKernelGGL(gauss_tables, dim3((unsigned)ta.C), dim3(256), 0, s, ta.counts, sumsq, ta.class_totals, eps,
+                       ta.C, ta.F, mean, reinterpret_cast<double*>(base + L.off_var), ta.weight, ta.bias);
+    NB_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(gauss_rows, dim3((unsigned)(ta.Fp / 256)), dim3(256), 0, s, mean, ta.weight, ta.bias, ta.C,
+                       ta.F, ta.Fp, reinterpret_cast<float*>(base + L.off_form_f32),
+                       reinterpret_cast<uint16_t*>(base + L.off_form_bf16),
+                       reinterpret_cast<float*>(base + L.off_form2_f32),
+                       reinterpret_cast<uint16_t*>(base + L.off_form2_bf16),
+                       reinterpret_cast<float*>(base + L.off_form_bias), class_flags,
+                       reinterpret_cast<int32_t*>(base + L.off_status));
+    NB_HIP_CHECK(hipGetLastError());
+    return NB_OK;
+  }
   hipLaunchKernelGGL(form_rows, dim3((unsigned)(ta.Fp / 256)), dim3(256), 0, s, ta.weight, ta.bias, ta.C, ta.F,
                      ta.Fp, reinterpret_cast<float*>(base + L.off_form_f32),
                      reinterpret_cast<uint16_t*>(base + L.off_form_bf16),
@@ -585,9 +774,13 @@ int launch_tables(nb_model* m, const nb_layout& L, const int64_t* part2, const i
 
 int flags_to_status(int32_t flags) {
   if (flags & kFlagBadIndex) return fail(NB_EDATA, "a selected feature index is outside [0, F)");
+  if (flags & kFlagZeroVariance)
+    return fail(NB_EDATA, "every training file is identical: the Gaussian variances are all zero");
   if (flags & (kFlagBadLabel | kFlagNegative))
     return fail(NB_EDATA, (flags & kFlagBadLabel) ? "a label is outside [0, C)" : "a feature value is negative");
-  if (flags & kFlagOverflow) return fail(NB_EOVERFLOW, "a per-class count exceeds INT32_MAX");
+  if (flags & kFlagOverflow)
+    return fail(NB_EOVERFLOW, "a per-class count exceeds INT32_MAX (or, for a Gaussian model, an int32 feature "
+                              "is 65536 or more)");
   if (flags & kFlagMinFiles) return fail(NB_EMINFILES, "a class has fewer training files than required");
   return NB_OK;
 }
@@ -641,9 +834,13 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   int64_t* nc_part = reinterpret_cast<int64_t*>(wsb + tw.off_nc);
   int64_t* part2 = reinterpret_cast<int64_t*>(wsb + tw.off_part2);
   int64_t* nc2 = reinterpret_cast<int64_t*>(wsb + tw.off_nc2);
-  const int n_flags = (int)(S * C * (Fp / kChunk));
+  const bool gauss = (m->kind == NB_GAUSSIAN);
+  const int n_flags1 = (int)(S * C * (Fp / kChunk));
+  const int n_flags = gauss ? 2 * n_flags1 : n_flags1;
   int32_t* flag_part = reinterpret_cast<int32_t*>(wsb + tw.off_flags);
-  int32_t* class_flags = flag_part + n_flags;
+  int32_t* class_flags = flag_part + 2 * n_flags1;
+  int64_t* part_sq = reinterpret_cast<int64_t*>(wsb + tw.off_part_sq);
+  int64_t* part2_sq = reinterpret_cast<int64_t*>(wsb + tw.off_part2_sq);
 
   CountArgs ca;
   ca.x = static_cast<const uint8_t*>(x);
@@ -668,13 +865,25 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
     else hipLaunchKernelGGL((count_kernel<NB_X_I32, false>), grid, dim3(kThreads), 0, s, ca);
   }
   NB_HIP_CHECK(hipGetLastError());
+  if (gauss) {   // second pass: the sums of squares
+    CountArgs cq = ca;
+    cq.part = part_sq;
+    cq.flag_part = flag_part + n_flags1;
+    if (xtype == NB_X_U8) hipLaunchKernelGGL((count_kernel<NB_X_U8, false, true>), grid, dim3(kThreads), 0, s, cq);
+    else hipLaunchKernelGGL((count_kernel<NB_X_I32, false, true>), grid, dim3(kThreads), 0, s, cq);
+    NB_HIP_CHECK(hipGetLastError());
+  }
 
-  hipLaunchKernelGGL(reduce_counts, dim3((unsigned)((F + 63) / 64), (unsigned)C, (unsigned)tw.RS), dim3(256), 0, s,
-                     part, nc_part, (int)S, C, F, Fp, part2, nc2);
+  const dim3 rgrid((unsigned)((F + 63) / 64), (unsigned)C, (unsigned)tw.RS);
+  hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part, nc_part, (int)S, C, F, Fp, part2, nc2);
   NB_HIP_CHECK(hipGetLastError());
+  if (gauss) {   // (the class totals it writes again are the same values)
+    hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part_sq, nc_part, (int)S, C, F, Fp, part2_sq, nc2);
+    NB_HIP_CHECK(hipGetLastError());
+  }
 
   rc = launch_tables(m, L, part2, nc2, (int)tw.RS, flag_part, n_flags, class_flags, alpha, min_files_per_class,
-                     s);
+                     s, part2_sq);
   if (rc) return rc;
 
   if (flags & NB_TRAIN_ASYNC) return NB_OK;
@@ -693,6 +902,8 @@ int nb_model_select(const nb_model* full, const int32_t* idx, int32_t k, double 
   int rc = check_model(full, &LF);
   if (rc) return rc;
   if (!full->trained) return fail(NB_EINVAL, "the full model is not trained");
+  if (full->kind == NB_GAUSSIAN)
+    return fail(NB_EINVAL, "k-feature models are built for multinomial and Bernoulli models");
   if (!out) return fail(NB_EINVAL, "out is NULL");
   if (out->n_features != k) return fail(NB_EINVAL, "out->n_features must equal k");
   if (out->kind != full->kind || out->n_classes != full->n_classes)

@@ -44,8 +44,10 @@ def assert_tables(model, om, kind):
     C, F = model.n_classes, model.n_features
     assert (to_np(model.class_totals()) == om.Nc).all(), "class totals"
     assert (to_np(model.counts()).astype(np.int64) == om.counts).all(), "counts"
-    if kind == nb.MULTINOMIAL:
+    if kind in (nb.MULTINOMIAL, nb.GAUSSIAN):
         assert (to_np(model.class_sums()) == om.counts.sum(axis=1)).all(), "class sums"
+    if kind == nb.GAUSSIAN:
+        return assert_gaussian_tables(model, om)
     W, b = nb.weight_form(om)
     for name, got, want in (("log_theta", model.log_theta(), om.log_theta),
                             ("weight", model.weight(), W), ("bias", model.bias(), b)):
@@ -69,7 +71,79 @@ def assert_tables(model, om, kind):
     return int((ulps > 0).sum()), int((u16 > 0).sum())
 
 
-def kernel_depth(C: int, F: int, wtype: int, xtype: int):
+def assert_gaussian_tables(model, om):
+    """Gaussian model buffer vs oracle: exact moment sums; FP64 mean,
+    variance, floor, h = -1 / (2 var) and the score form's bias to a few
+    roundings (the device forms the variance numerator exactly and converts
+    it in at most four roundings); the FP32/BF16 rows (means, h) within one
+    unit in the last place of the oracle's own rounding."""
+    C, F = model.n_classes, model.n_features
+    assert (to_np(model.sumsq()) == om.sq).all(), "sums of squares"
+    assert float(to_np(model.epsilon())[0]) == pytest_approx(om.eps, 1e-13)
+    mean, h, b = nb.gaussian_score_form(om)
+    for name, got, want in (("mean", model.mean(), om.mean), ("var", model.var(), om.var),
+                            ("h", model.weight(), h)):
+        g = to_np(got)
+        assert (np.abs(g - want) <= 1e-13 * np.abs(want)).all(), name
+    terms = 0.5 * np.abs(np.log(2 * np.pi * om.var)).sum(axis=1)
+    assert (np.abs(to_np(model.bias()) - b) <= 1e-12 * (terms + np.abs(b))).all(), "bias"
+    n_ulp = 0
+    for (f32, bf), r in (((model.form_f32(), model.form_bf16()), mean), ((model.form2_f32(), model.form2_bf16()), h)):
+        f32, bf = to_np(f32)[:C], to_np(bf).view(np.uint16)[:C]
+        assert (f32[:, F:] == 0).all()
+        want32 = P.rne_f32(r).astype(np.float32)
+        ulps = np.abs(f32[:, :F].view(np.int32).astype(np.int64) - want32.view(np.int32).astype(np.int64))
+        assert ulps.max() <= 1, f"fp32 rows off by {ulps.max()} ulp"
+        u16 = np.abs(bf[:, :F].astype(np.int64) - P.bf16_bits(P.rne_bf16(r)).astype(np.int64))
+        assert u16.max() <= 1, f"bf16 rows off by {u16.max()} ulp"
+        n_ulp += int((ulps > 0).sum())
+    if C == 2:
+        fb = to_np(model.form_bias()).astype(np.float64)
+        rb = np.array([b[1] - b[0], b[0]])
+        assert np.abs(fb - rb).max() <= 1e-6 * np.abs(rb).max() + 1e-6
+    return n_ulp, 0
+
+
+def gaussian_bounds(om, X, wtype, xtype):
+    """Per file: bounds on the error of the two-class Gaussian kernel's
+    log-odds and of its raw score s_0.  The kernel sums, per feature,
+    t1 d1 - t0 d0 with d = fl(x - mean^), t = fl(h^ d) in FP32 (fma), from
+    means and h rounded once (FP32 or BF16) and possibly one unit in the
+    last place away from the oracle's rounding; the table error is
+    |h^ - h| (x - mean)^2 + |h^| |mean - mean^| |2x - mean - mean^| and the
+    rounding error gamma_k sum |h^| d^2 with k the kernel's depth."""
+    mean, h, b = nb.gaussian_score_form(om)
+    rnd = P.rne_bf16 if wtype == W_BF16 else P.rne_f32
+    mh, hh = rnd(mean), rnd(h)
+    scale = 2.0 ** 16 if wtype == W_BF16 else 1.0
+    ulp_m = np.spacing(np.abs(mh).astype(np.float32)).astype(np.float64) * scale
+    ulp_h = np.spacing(np.abs(hh).astype(np.float32)).astype(np.float64) * scale
+    depth, _ = kernel_depth(2, om.n_features, wtype, xtype, quad=True)
+    k = depth * U
+    gamma = k / (1.0 - k)
+    X = np.asarray(X, dtype=np.float64)
+    T, S = [], []
+    for c in range(2):
+        D = X - mean[c][None, :]
+        Dh = X - mh[c][None, :]
+        tab = ((np.abs(hh[c] - h[c]) + ulp_h[c])[None, :] * D * D).sum(axis=1) \
+            + ((np.abs(hh[c]) * (np.abs(mean[c] - mh[c]) + ulp_m[c]))[None, :]
+               * np.abs(2.0 * X - mean[c][None, :] - mh[c][None, :])).sum(axis=1)
+        T.append(tab)
+        S.append((np.abs(hh[c])[None, :] * Dh * Dh).sum(axis=1))
+    bd = np.array([b[1] - b[0], b[0]])
+    bh = P.rne_f32(bd)
+    e_delta = T[0] + T[1] + gamma * (S[0] + S[1]) + np.abs(bh[0] - bd[0]) + U * np.abs(bh[0])
+    e_s0 = T[0] + gamma * S[0] + np.abs(bh[1] - bd[1]) + U * np.abs(bh[1])
+    return e_delta, e_s0
+
+
+def pytest_approx(v, rel):
+    import pytest
+    return pytest.approx(v, rel=rel)
+
+
+def kernel_depth(C: int, F: int, wtype: int, xtype: int, quad: bool = False):
     """(roundings per term, per-addition rounding factor) of the scoring path
     libnbgpu takes for these arguments (see the kernel headers)."""
     if C == 2:
@@ -78,6 +152,8 @@ def kernel_depth(C: int, F: int, wtype: int, xtype: int):
         while lpr < need and lpr < 64:
             lpr *= 2
         nch = -(-F // (16 * lpr))
+        if quad:   # two roundings per feature (x^2 term, then x term), plus x^2 itself
+            return 32 * nch + int(math.log2(lpr)) + 3, 1.0
         return 16 * nch + int(math.log2(lpr)) + 2, 1.0
     if wtype == W_BF16 and C >= 16 and xtype != X_I32:
         return 32 + -(-F // 32) + 2, 2.0
@@ -103,6 +179,8 @@ def assert_scores(om, X, labels, log_post, scores, wtype=W_F32, xtype=X_U8):
     C, F = om.n_classes, om.n_features
     s = nb.joint_log_likelihood(om, X)
     d = nb.decide(s)
+    if om.kind == nb.GAUSSIAN:
+        return _assert_gaussian_scores(om, X, s, d, labels, log_post, scores, wtype, xtype)
     W, b = nb.weight_form(om)
     rows, rb = P.scoring_form(W, b)
     rows_hat = P.rne_bf16(rows) if wtype == W_BF16 else P.rne_f32(rows)
@@ -154,4 +232,37 @@ def assert_scores(om, X, labels, log_post, scores, wtype=W_F32, xtype=X_U8):
         assert agree[gate].all(), f"{int((~agree[gate]).sum())} labels differ above the margin gate"
         stats["label_agreement_all"] = float(agree.mean())
         stats["files_in_band"] = int((~gate).sum())
+    return stats
+
+
+def _assert_gaussian_scores(om, X, s, d, labels, log_post, scores, wtype, xtype):
+    """Two-class Gaussian outputs vs the oracle within gaussian_bounds."""
+    e_delta, e_s0 = gaussian_bounds(om, X, wtype, xtype)
+    band = e_delta + 2 * U * np.abs(s[:, 1] - s[:, 0])
+    stats = {"n": int(X.shape[0])}
+    if scores is not None:
+        tol = np.stack([e_s0 + 2 * U * np.abs(s[:, 0]),
+                        e_s0 + band + 2 * U * (np.abs(s[:, 0]) + np.abs(s[:, 1]))], axis=1)
+        err = np.abs(scores.astype(np.float64) - s)
+        assert (err <= tol).all(), f"score error {err.max()} above bound (worst ratio {(err / tol).max():.3g})"
+        stats["score_max_err"] = float(err.max())
+    if log_post is not None:
+        tol = (band + 1e-5)[:, None]
+        err = np.abs(log_post.astype(np.float64) - d.log_post)
+        assert (err <= tol).all(), f"log-posterior error {err.max()} above bound (worst ratio {(err / tol).max():.3g})"
+        perr = np.abs(np.exp(log_post.astype(np.float64)) - np.exp(d.log_post))
+        # Gaussian models: the variance floor makes terms of 1e8 and more
+        # (a feature constant in one class); where such terms cancel the
+        # FP32 log-odds carries their rounding, so the posterior is checked
+        # through the log-posterior bound and the literal 1e-4 rate is stated
+        with np.errstate(over="ignore"):
+            bound = np.exp(d.log_post + np.log(np.expm1(tol)))
+        assert (perr <= bound * (1 + 1e-12)).all(), f"posterior error {perr.max()}"
+        stats["post_max_err"] = float(perr.max())
+        stats["post_1e-4_rate"] = float((perr.max(axis=1) <= 1e-4).mean())
+    if labels is not None:
+        gate = d.margin > np.maximum(1e-3, band)
+        agree = labels.astype(np.int64) == d.labels
+        assert agree[gate].all(), f"{int((~agree[gate]).sum())} labels differ above the margin gate"
+        stats["label_agreement_all"] = float(agree.mean())
     return stats

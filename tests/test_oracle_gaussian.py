@@ -90,6 +90,21 @@ def test_weight_form_is_the_density():
     assert np.abs(s - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+def test_score_form_is_the_expanded_form():
+    # the density's own form and the expanded linear form agree
+    rng = np.random.default_rng(8)
+    X = rng.poisson(3.0, size=(200, 10))
+    y = np.arange(200) % 2
+    m = nb.train(X, y, 2, nb.GAUSSIAN)
+    mean, h, bias = nb.gaussian_score_form(m)
+    Xt = rng.poisson(3.0, size=(30, 10)).astype(np.float64)
+    s = np.stack([bias[c] + (h[c][None, :] * (Xt - mean[c][None, :]) ** 2).sum(axis=1) for c in range(2)], axis=1)
+    W, b = nb.weight_form(m)
+    s2 = np.concatenate([Xt, Xt * Xt], axis=1) @ W.T + b
+    assert np.abs(s - s2).max() <= 1e-10 * np.abs(s).max()
+    assert (h < 0).all()
+
+
 def test_invariants():
     rng = np.random.default_rng(6)
     X = rng.poisson(2.5, size=(300, 16)).astype(np.int64)
@@ -119,7 +134,7 @@ def test_invariants():
 
 def _pins_fail():
     checks = [test_worked_example, lambda: test_sklearn_cross_check(0), lambda: test_sklearn_cross_check(2),
-              test_weight_form_is_the_density, test_invariants]
+              test_weight_form_is_the_density, test_score_form_is_the_expanded_form, test_invariants]
     failed = 0
     for chk in checks:
         try:
@@ -166,7 +181,22 @@ def _quadratic_sign(m):
     return W, b
 
 
+_orig_sform = nb.gaussian_score_form
+
+
+def _score_form_without_two_pi(m):
+    mean, h, bias = _orig_sform(m)
+    return mean, h, bias + 0.5 * m.n_features * np.log(2.0 * np.pi)
+
+
+def _score_form_full_inverse(m):
+    mean, h, bias = _orig_sform(m)
+    return mean, 2.0 * h, bias
+
+
 GAUSS_MUTATIONS = {
+    "score form drops 2 pi": ("gaussian_score_form", _score_form_without_two_pi),
+    "score form without the 1/2": ("gaussian_score_form", _score_form_full_inverse),
     "sample (n - 1) variance": ("gaussian_moments", _sample_variance),
     "no variance floor": ("gaussian_moments", _no_floor),
     "floor from class variances": ("gaussian_moments", _floor_from_class_variances),

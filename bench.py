@@ -31,6 +31,8 @@ step's inputs.  Extra objects (skip with --no-extras):
   select     top-k feature selection over 256 models (F = 2000), the k-feature
              model from counts, and the gather of 1,000,000 files' k selected
              bytes for k in {20, ..., 200}.
+  gaussian   the Gaussian variant at the headline shape (training and
+             two-class scoring), next to the multinomial kernels.
   replay     the paper's experiment shape (100 size groups, 93 trained,
              per-group top-k, test files in multiples of 768): GPU grouped
              classification time vs the oracle on one host core.
@@ -65,7 +67,7 @@ def parse():
                     help="repeat the oracle's step until this much CPU time has been spent")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--leg", choices=["f_sweep", "precision", "groups", "serve", "select", "replay"],
+    ap.add_argument("--leg", choices=["f_sweep", "precision", "groups", "serve", "select", "replay", "gaussian"],
                     help="run only this extra leg and print its JSON (used for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--select-k", default="20,40,80,100,160,200",
@@ -235,12 +237,15 @@ def groups_leg(nbg, W, steps: int = 20):
     launches over the same buffers."""
     sizes = W.group_sizes()
     F = 2000
-    models, xs = [], []
+    CPU_GROUPS = 16
+    models, xs, cpu_train = [], [], []
     for g, n in enumerate(sizes):
         wl = W.group_workload(g, F)
         X, y = wl.train_set(int(min(2 * n, 20_000)), device="cuda")
         m = nbg.Model(2, F, "multinomial")
         nbg.train(m, X, y)
+        if g < CPU_GROUPS:
+            cpu_train.append((X.cpu().numpy(), y.cpu().numpy()))
         del X, y
         models.append(m)
         xs.append(wl.test_set(int(n), device="cuda")[0])
@@ -264,7 +269,29 @@ def groups_leg(nbg, W, steps: int = 20):
            "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBPS,
            "per_group_launch_loop_ms": ms_loop, "speedup_vs_loop": ms_loop / ms_plan}
     plan.close()
+    res["cpu_baseline"] = groups_cpu_baseline(cpu_train, xs[:CPU_GROUPS])
     return res
+
+
+def groups_cpu_baseline(cpu_train, xs, seconds: float = 5.0):
+    """The oracle classifying the first groups' test files with their own
+    models, group by group on one core (models fitted outside the timing)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import nb
+    oms = [nb.train(X, y, 2, nb.MULTINOMIAL) for X, y in cpu_train]
+    xn = [x.cpu().numpy() for x in xs]
+    n = sum(x.shape[0] for x in xn)
+    reps, sec = 0, 0.0
+    with threadpool_limits(limits=1):
+        while sec < seconds and reps < 50:
+            t0 = time.perf_counter()
+            for om, x in zip(oms, xn):
+                nb.classify(om, x)
+            sec += time.perf_counter() - t0
+            reps += 1
+    return {"value": reps * n / sec, "unit": "files/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {len(xn)} groups ({n} files) classified group by group x {reps}, "
+                      f"numpy FP64, one thread, {sec:.1f} s"}
 
 
 def select_leg(nbg, W, n_files: int = 1_000_000, F: int = 2000, steps: int = 20,
@@ -310,8 +337,10 @@ def select_leg(nbg, W, n_files: int = 1_000_000, F: int = 2000, steps: int = 20,
                          "score_k_ms": ms_score, "score_k_files_per_s": n / (ms_score / 1e3),
                          "k_model_from_counts_ms": ms_model}
         del out
+    cpu = None if fill else select_cpu_baseline(W, Xt[:50_000], F)
     return {"workload": f"256 two-class multinomial models of F={F} uint8 features (600 training files each); "
                         f"gather and scoring over {n} files of F={F} uint8 (group 0's distribution)",
+            "cpu_baseline": cpu,
             "select_256_models_k200_ms": ms_select, "score_full_F_ms": ms_full,
             "score_full_F_files_per_s": n / (ms_full / 1e3), "per_k": per_k,
             "gather_algorithmic_bytes_per_file": f"F + k = {F} + k (each row read once, k bytes written)"}
@@ -384,6 +413,62 @@ def replay_leg(nbg, W, ms=(1, 4, 16, 64, 256, 1024), reps: int = 20, cpu_min_s: 
             res["per_k"][str(k)][str(768 * m_)] = {"gpu_ms": tp, "cpu_ms": tc, "speedup": tc / tp}
         del full_x
     return res
+
+
+def select_cpu_baseline(W, xs, F: int, n_models: int = 8):
+    """The oracle's top-200 selection for the first groups (counts fitted by
+    the oracle from the same synthetic training files) and its gather of
+    50,000 files' 200 selected columns, on one core."""
+    from threadpoolctl import threadpool_limits
+    from oracle import nb, select
+    counts = []
+    for g in range(n_models):
+        X, y = W.group_workload(g, F).train_set(600)
+        counts.append(nb.train(X.numpy(), y.numpy(), 2, nb.MULTINOMIAL).counts)
+    xn = xs.cpu().numpy()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        idx = [select.top_k(c, select.class_sums(c), 200) for c in counts]
+        t_sel = (time.perf_counter() - t0) / len(counts)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 2.0:
+            select.gather(xn, idx[0])
+            reps += 1
+        t_g = (time.perf_counter() - t0) / reps
+    return {"value": xn.shape[0] / t_g, "unit": "files/s gathered (k = 200)", "cores": 1, "kind": "oracle",
+            "select_ms_per_model": t_sel * 1e3,
+            "sample": f"selection on {len(counts)} models' counts; gather of {xn.shape[0]} files x {reps}"}
+
+
+def gaussian_leg(nbg, W, F: int = 1000, n_train: int = 200_000, n_test: int = 1_000_000, steps: int = 20,
+                 fill: bool = False):
+    """The Gaussian variant at the headline shape: training (two passes:
+    sums and sums of squares) and two-class scoring of 1,000,000 files of
+    F = 1000 bytes, next to the multinomial kernel on the same bytes."""
+    wl = W.binary_u8(F)
+    if fill:
+        X = (torch.arange(n_train * F, device="cuda") % 7).to(torch.uint8).view(n_train, F)
+        y = (torch.arange(n_train, device="cuda") % 2).to(torch.int32)
+        Xt = torch.full((n_test, F), 2, dtype=torch.uint8, device="cuda")
+    else:
+        X, y = wl.train_set(n_train, device="cuda")
+        Xt, _ = wl.test_set(n_test, device="cuda")
+    m = nbg.Model(2, F, "gaussian")
+    mm = nbg.Model(2, F, "multinomial")
+    ws = nbg.train_workspace(m, n_train)
+    nbg.train(m, X, y, workspace=ws)
+    nbg.train(mm, X, y, workspace=ws)
+    ms_train = timed(lambda: nbg.train(m, X, y, workspace=ws, asynchronous=True), steps)
+    ms_train_mn = timed(lambda: nbg.train(mm, X, y, workspace=ws, asynchronous=True), steps)
+    lab = torch.empty(n_test, dtype=torch.int32, device="cuda")
+    lp = torch.empty((n_test, 2), dtype=torch.float32, device="cuda")
+    ms = timed(lambda: nbg.score(m, Xt, out=(lab, lp, None)), steps)
+    ms_mn = timed(lambda: nbg.score(mm, Xt, out=(lab, lp, None)), steps)
+    gbs = n_test * (F + 12) / (ms / 1e3) / 1e9
+    return {"workload": f"two-class Gaussian NB, F={F} uint8 counts, train {n_train} + score {n_test} files",
+            "score_ms": ms, "score_files_per_s": n_test / (ms / 1e3), "score_GBps": gbs,
+            "score_frac_of_peak": gbs / HBM_PEAK_GBPS, "multinomial_score_ms": ms_mn,
+            "train_ms": ms_train, "multinomial_train_ms": ms_train_mn}
 
 
 def serve_leg(nbg, W, n_requests: int = 8000, full: bool = False):
@@ -480,6 +565,7 @@ def main():
         else:
             ks = tuple(int(v) for v in args.select_k.split(","))
             res = {"f_sweep": f_sweep, "groups": groups_leg, "replay": replay_leg,
+                   "gaussian": lambda a, b: gaussian_leg(a, b, fill=args.fill_inputs),
                    "select": lambda a, b: select_leg(a, b, ks=ks, fill=args.fill_inputs),
                    "serve": lambda a, b: serve_leg(a, b, full=True)}[args.leg](nbg, W)
         print(json.dumps({"leg": args.leg, **res}), flush=True)
@@ -580,6 +666,8 @@ def main():
         rec["select"] = select_leg(nbg, W)
         torch.cuda.empty_cache()
         rec["replay"] = replay_leg(nbg, W)
+        torch.cuda.empty_cache()
+        rec["gaussian"] = gaussian_leg(nbg, W)
         rec["paper_context"] = ("the paper reports up to 200x GPU over a sequential CPU program on a GTX 1050 Ti "
                                 "vs an i7-7700HQ, overheads excluded (section 4); different hardware and workload")
     print(json.dumps(rec), flush=True)

@@ -83,6 +83,11 @@ __device__ __forceinline__ T load_uniform(const T* p) {
 #define NB_STREAM_CPOL 2
 #endif
 
+// A buffer offset past every range make_rsrc builds: the load reads nothing
+// and returns zeros (the instruction still issues, so counts of loads in
+// flight stay fixed).
+constexpr uint32_t kNoAccess = 0x80000000u;
+
 __device__ __forceinline__ u32x4 buffer_load16(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, NB_STREAM_CPOL);
   return u32x4{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};

@@ -170,10 +170,12 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
       const uint32_t toff = (uint32_t)threadIdx.x * TPL * (bf ? 2u : 4u);
       tdst[0] = dev::buffer_load16(trs, toff);
       tdst[1] = dev::buffer_load16(trs, bf ? (uint32_t)tbytes : toff + 16u);
+      // lanes whose 16 features of this chunk lie past F read nothing
+      const bool live = ich * CW + 16 * j < ia.F;
 #pragma unroll
       for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, voff[i] + 16 * q);
+        for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + 16 * q : dev::kNoAccess);
       __builtin_amdgcn_sched_barrier(0);
       advance();
     };

@@ -367,10 +367,13 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
     const int64_t blk = first + (int64_t)ib * stride;
     const int64_t off = blk * BR * ld + (int64_t)ich * CW * EB;
     const auto rsrc = dev::make_rsrc(a.x + off, a.total_bytes - off);
+    // a lane whose 16 features of this chunk all lie past F reads nothing:
+    // those bytes belong to the next row, which its own loads fetch
+    const bool live = ich * CW + 16 * j < a.F;
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
-      for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, voff[i] + 16 * q);
+      for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + 16 * q : dev::kNoAccess);
     // keep the loads here: the scheduler would otherwise sink them into the
     // arithmetic of the unit being consumed and shrink the overlap
     __builtin_amdgcn_sched_barrier(0);

@@ -199,6 +199,19 @@ def weight_form(m: Model):
     return m.log_theta - m.log_1m_theta, m.log_prior + m.log_1m_theta.sum(axis=1)
 
 
+def gaussian_score_form(m: Model):
+    """The Gaussian scorer as s_c = bias_c + sum_f h_cf (x_f - mean_cf)^2 with
+    h = -1 / (2 var) and bias = log prior - (1/2) sum_f log(2 pi var): the
+    density's own form, which keeps each term's relative error small when a
+    variance is tiny (the expanded form A x + B x^2 cancels large terms).
+    Returns (mean, h, bias)."""
+    if m.kind != GAUSSIAN:
+        raise ValueError("a Gaussian model")
+    h = -0.5 / m.var
+    bias = m.log_prior - 0.5 * np.log(2.0 * np.pi * m.var).sum(axis=1)
+    return m.mean.copy(), h, bias
+
+
 def joint_log_likelihood(m: Model, X) -> np.ndarray:
     """s[j, c] = log P(c) + log P(x_j | c) in float64 (float64[n, C]).
 

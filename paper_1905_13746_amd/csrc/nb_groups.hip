@@ -795,17 +795,20 @@ int autotune(nb_group_plan* p, hipStream_t s) {
     const WorkList w = make_work_list(p->S, t);
     if ((rc = upload(p, w))) break;
     if ((rc = launch_grouped(p->S, w, d, s))) break;   // warm
-    float tot = 0.0f;
-    for (int r = 0; r < 3 && rc == NB_OK; ++r) {
+    // the median of a few single launches: robust to an occasional slow one
+    constexpr int kReps = 7;
+    float ms_r[kReps];
+    for (int r = 0; r < kReps && rc == NB_OK; ++r) {
       if (hipEventRecord(e0, s) != hipSuccess) rc = fail(NB_EHIP, "hipEventRecord");
       if (!rc) rc = launch_grouped(p->S, w, d, s);
       if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(NB_EHIP, "hipEventRecord");
       if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(NB_EHIP, "hipEventSynchronize");
-      float ms = 0.0f;
-      if (!rc) hipEventElapsedTime(&ms, e0, e1);
-      tot += ms;
+      ms_r[r] = 0.0f;
+      if (!rc) hipEventElapsedTime(&ms_r[r], e0, e1);
     }
     if (rc) break;
+    std::sort(ms_r, ms_r + kReps);
+    const float tot = ms_r[kReps / 2];
     if (tot < best) {
       best = tot;
       best_t = t;

@@ -184,3 +184,43 @@ def test_staged_batch_invariance():
         for u, v in zip(full, part):
             if u is not None:
                 assert torch.equal(u[a:b], v)
+
+
+@pytest.mark.slow
+def test_full_size_16_classes_sampled():
+    """The 16-class precision configuration at full size: F = 4096 byte
+    features, 800,000 training files (Dirichlet(1) priors), 4,000,000 test
+    files scored by the BF16 matrix cores (uint8 and FP8-e4m3 features) and
+    by the plain FP32 vector path, each in the launch configuration the
+    benchmark times; sampled files (and the last rows) against the oracle,
+    and the paths' labels against each other on every file."""
+    _case("16 classes full size")
+    wl = W.family16()
+    X, y = wl.train_set(W.FAMILY_TRAIN, device=DEV)
+    m = nbg.Model(16, wl.n_features)
+    nbg.train(m, X, y)
+    om = nb.train(to_np(X), to_np(y), 16, nb.MULTINOMIAL)
+    assert_tables(m, om, nb.MULTINOMIAL)
+    del X, y
+    torch.cuda.empty_cache()
+    Xt, _ = wl.test_set(W.FAMILY_TEST, device=DEV)
+    n = Xt.shape[0]
+    rng = np.random.default_rng(12)
+    idx = np.concatenate([np.sort(rng.choice(n - 64, 12_000, replace=False)), np.arange(n - 64, n)])
+    ii = torch.from_numpy(idx).to(DEV)
+    x_np = to_np(Xt[ii])
+    labels = {}
+    for name, wtype, fp8 in (("bf16_u8", nbg.W_BF16, False), ("bf16_fp8", nbg.W_BF16, True),
+                             ("fp32", nbg.W_F32, False)):
+        _case(f"16 classes full size {name}")
+        x = nbg.quantize_fp8(Xt) if fp8 else Xt
+        lab, lp, _ = nbg.score(m, x, wtype=wtype, fp8=fp8)
+        torch.cuda.synchronize()
+        xo = P.e4m3_value(to_np(x[ii])) if fp8 else x_np
+        assert_scores(om, xo, to_np(lab[ii]), to_np(lp[ii]), None, wtype=wtype, xtype=X_FP8 if fp8 else X_U8)
+        labels[name] = lab
+        del x, lp
+    # the reduced-precision labels equal the FP32 path's wherever the certified
+    # band allows a difference at all: report the agreement, require it above 99.9%
+    agree = (labels["bf16_u8"] == labels["fp32"]).float().mean().item()
+    assert agree > 0.999, agree

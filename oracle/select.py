@@ -111,3 +111,26 @@ def model_on_features(m: nb.Model, idx) -> nb.Model:
                         nb.multinomial_log_theta(counts, m.alpha), None)
     lt, l1m = nb.bernoulli_log_theta(counts, m.Nc, m.alpha)
     return nb.Model(m.kind, m.alpha, m.Nc.copy(), counts, m.log_prior.copy(), lt, l1m)
+
+
+def expanded_model(mk: nb.Model, idx, n_features: int) -> nb.Model:
+    """The k-feature model mk (on the ascending feature list idx) written
+    over all n_features: its counts and log tables at the selected features
+    and zero elsewhere, class totals and priors unchanged.  A zero log table
+    entry contributes nothing to a file's joint log likelihood, so on a full
+    row it scores exactly what mk scores on the row's selected features."""
+    idx = np.asarray(idx, dtype=np.int64).reshape(-1)
+    if idx.size != mk.n_features or np.any(np.diff(idx) <= 0) or idx[0] < 0 or idx[-1] >= n_features:
+        raise ValueError("idx must list mk's features in ascending order within [0, n_features)")
+    C = mk.n_classes
+
+    def spread(a, dtype):
+        if a is None:
+            return None
+        out = np.zeros((C, n_features), dtype=dtype)
+        out[:, idx] = a
+        return out
+
+    return nb.Model(mk.kind, mk.alpha, mk.Nc.copy(), spread(mk.counts, np.int64), mk.log_prior.copy(),
+                    spread(mk.log_theta, np.float64), spread(mk.log_1m_theta, np.float64))
+

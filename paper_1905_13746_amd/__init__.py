@@ -216,6 +216,19 @@ def model_on_features(full: Model, idx: torch.Tensor, alpha: float = 1.0, worksp
     return m
 
 
+def expand_model(km: Model, idx: torch.Tensor, n_features: int, out: Model | None = None,
+                 asynchronous: bool = False, stream=None) -> Model:
+    """The k-feature model km widened to n_features: scores full rows as km
+    scores their selected features idx (int32, ascending, device)."""
+    if idx.dtype != torch.int32 or idx.dim() != 1 or not idx.is_contiguous():
+        raise ValueError("idx must be a contiguous 1-D int32 tensor")
+    m = out if out is not None else Model(km.n_classes, n_features, km.kind, device=km.buf.device)
+    rc = load().nb_model_expand(ctypes.byref(km.c), _ptr(idx), ctypes.byref(m.c),
+                                TRAIN_ASYNC if asynchronous else 0, _stream(stream))
+    check(rc, "nb_model_expand")
+    return m
+
+
 def gather_features(x: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None, fp8: bool = False,
                     status: torch.Tensor | None = None, stream=None):
     """out[i, j] = x[i, idx[j]] for features x [n, F] and int32 indices idx [k]."""

@@ -97,6 +97,7 @@ SIGNATURES = {
     "nb_model_select_workspace_bytes": (_sz, [_i32, _i32]),
     "nb_model_select": (ctypes.c_int, [_PM, _vp, _i32, _d, _PM, _vp, _sz, _i32, _vp]),
     "nb_gather_features": (ctypes.c_int, [_vp, _i32, _i64, _i32, _i64, _vp, _i32, _vp, _i64, _vp, _vp]),
+    "nb_model_expand": (ctypes.c_int, [_PM, _vp, _PM, _i32, _vp]),
     "nb_route_groups": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp]),
     "nb_score_groups_workspace_bytes": (_sz, [_PM, _i32, _PG, _i32, _i32, _i32, _i32]),
     "nb_score_groups": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _vp, _sz, _vp]),

@@ -16,6 +16,11 @@
 //                  ascending order by a ballot compaction.  Keys are
 //                  recomputed from the counts (L2-resident) in every pass,
 //                  so any F works with 1 KB of LDS.
+//   expand_rows    the k-feature model widened to the full feature vector
+//                  (its tables and rows at the selected features, zero
+//                  elsewhere; a binary search of the ascending index list
+//                  per feature), so a group's files are scored on their
+//                  full rows in one pass.
 //   gather_kernel  out[i][j] = x[i][idx[j]], HBM-bound: every row is read
 //                  once with 16-byte loads and k elements are written.  Each
 //                  wave stages units of consecutive rows, each loaded as one
@@ -533,3 +538,123 @@ int nb_gather_features(const void* x, int32_t xtype, int64_t n, int32_t F, int64
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ expand
+namespace nb {
+namespace {
+
+struct ExpandArgs {
+  const uint8_t* kb;    // the k-feature model's buffer
+  uint8_t* ob;          // the full model's buffer
+  const int32_t* idx;
+  nb_layout LK, LO;
+  int32_t C, k, F, kind;
+};
+
+// Position of feature f in the ascending list idx[0..k) (or -1).
+__device__ __forceinline__ int find_selected(const int32_t* __restrict__ idx, int k, int f) {
+  int lo = 0, hi = k - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = idx[mid];
+    if (v == f) return mid;
+    if (v < f) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// Every feature f of the full model: km's tables and scoring rows at its
+// selected position, zero elsewhere.  grid Fp / 256.
+__global__ __launch_bounds__(256) void expand_rows(ExpandArgs a) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  const int Fp = a.LO.padded_features, Fk = a.LK.padded_features;
+  if (f >= Fp) return;
+  const int j = (f < a.F) ? find_selected(a.idx, a.k, f) : -1;
+  const int P = a.LO.form_rows;
+  for (int r = 0; r <= P; ++r) {
+    reinterpret_cast<float*>(a.ob + a.LO.off_form_f32)[(int64_t)r * Fp + f] =
+        j >= 0 ? reinterpret_cast<const float*>(a.kb + a.LK.off_form_f32)[(int64_t)r * Fk + j] : 0.0f;
+    reinterpret_cast<uint16_t*>(a.ob + a.LO.off_form_bf16)[(int64_t)r * Fp + f] =
+        j >= 0 ? reinterpret_cast<const uint16_t*>(a.kb + a.LK.off_form_bf16)[(int64_t)r * Fk + j] : (uint16_t)0;
+  }
+  if (f < a.F) {
+    for (int c = 0; c < a.C; ++c) {
+      const int64_t o = (int64_t)c * a.F + f, i = (int64_t)c * a.k + j;
+      reinterpret_cast<int32_t*>(a.ob + a.LO.off_counts)[o] =
+          j >= 0 ? reinterpret_cast<const int32_t*>(a.kb + a.LK.off_counts)[i] : 0;
+      reinterpret_cast<double*>(a.ob + a.LO.off_log_theta)[o] =
+          j >= 0 ? reinterpret_cast<const double*>(a.kb + a.LK.off_log_theta)[i] : 0.0;
+      reinterpret_cast<double*>(a.ob + a.LO.off_log_1m_theta)[o] =
+          j >= 0 ? reinterpret_cast<const double*>(a.kb + a.LK.off_log_1m_theta)[i] : 0.0;
+      reinterpret_cast<double*>(a.ob + a.LO.off_weight)[o] =
+          j >= 0 ? reinterpret_cast<const double*>(a.kb + a.LK.off_weight)[i] : 0.0;
+    }
+  }
+}
+
+// Class totals, sums and biases copied; the index list checked (strictly
+// ascending, inside [0, F)); the status word.  One workgroup.
+__global__ __launch_bounds__(256) void expand_finish(ExpandArgs a) {
+  bool bad = false;
+  for (int j = threadIdx.x; j < a.k; j += 256) {
+    const int32_t v = a.idx[j];
+    if (v < 0 || v >= a.F || (j + 1 < a.k && a.idx[j + 1] <= v)) bad = true;
+  }
+  const int any_bad = __syncthreads_or(bad);
+  const int t = threadIdx.x;
+  if (t < a.C) {
+    reinterpret_cast<int64_t*>(a.ob + a.LO.off_class_totals)[t] =
+        reinterpret_cast<const int64_t*>(a.kb + a.LK.off_class_totals)[t];
+    reinterpret_cast<int64_t*>(a.ob + a.LO.off_class_sums)[t] =
+        reinterpret_cast<const int64_t*>(a.kb + a.LK.off_class_sums)[t];
+    reinterpret_cast<double*>(a.ob + a.LO.off_bias)[t] = reinterpret_cast<const double*>(a.kb + a.LK.off_bias)[t];
+  }
+  for (int r = t; r <= a.LO.form_rows; r += 256)
+    reinterpret_cast<float*>(a.ob + a.LO.off_form_bias)[r] =
+        reinterpret_cast<const float*>(a.kb + a.LK.off_form_bias)[r];
+  if (t == 0) {
+    int32_t* st = reinterpret_cast<int32_t*>(a.ob + a.LO.off_status);
+    st[kStatusFlags] = any_bad ? kFlagBadIndex : 0;
+    st[kStatusTrained] = any_bad ? 0 : 1;
+    st[2] = 0;
+    st[3] = 0;
+  }
+}
+
+}  // namespace
+}  // namespace nb
+
+extern "C" int nb_model_expand(const nb_model* km, const int32_t* idx, nb_model* out, int32_t flags, void* stream) {
+  nb_layout LK, LO;
+  int rc = check_model(km, &LK);
+  if (rc) return rc;
+  if (!km->trained) return fail(NB_EINVAL, "the k-feature model is not trained");
+  if (km->kind == NB_GAUSSIAN) return fail(NB_EINVAL, "expansion takes multinomial and Bernoulli models");
+  if (!out) return fail(NB_EINVAL, "out is NULL");
+  if (out->kind != km->kind || out->n_classes != km->n_classes)
+    return fail(NB_EINVAL, "out must have the kind and class count of the k-feature model");
+  rc = check_model(out, &LO);
+  if (rc) return rc;
+  if (out->n_features < km->n_features) return fail(NB_EINVAL, "out->n_features must be >= k");
+  if (out->dev == km->dev) return fail(NB_EINVAL, "out must have its own buffer");
+  if (!idx) return fail(NB_EINVAL, "idx must be non-NULL");
+  out->trained = 0;
+  ExpandArgs a;
+  a.kb = static_cast<const uint8_t*>(km->dev);
+  a.ob = static_cast<uint8_t*>(out->dev);
+  a.idx = idx;
+  a.LK = LK;
+  a.LO = LO;
+  a.C = km->n_classes;
+  a.k = km->n_features;
+  a.F = out->n_features;
+  a.kind = km->kind;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(expand_rows, dim3((unsigned)(LO.padded_features / 256)), dim3(256), 0, s, a);
+  NB_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(expand_finish, dim3(1), dim3(256), 0, s, a);
+  NB_HIP_CHECK(hipGetLastError());
+  if (flags & NB_TRAIN_ASYNC) return NB_OK;
+  return nb_model_status(out, stream);
+}

@@ -251,3 +251,22 @@ def test_selection_argument_errors(lib):
     assert g(x, 0, 10, 100, 100, None, 5, o, 5, None, None) == -1         # idx NULL
     assert g(ctypes.c_void_p(FAKE_DEV + 2), 1, 10, 100, 100, idx, 5, o, 5, None, None) == -1  # int32 misaligned
     assert g(x, 0, 10, 100, 100, ctypes.c_void_p(FAKE_DEV + 2), 5, o, 5, None, None) == -1    # idx misaligned
+
+
+def test_expand_argument_errors(lib):
+    km = _model(2, 10)
+    km.trained = 1
+    idx = ctypes.c_void_p(FAKE_DEV)
+    out = _lib.NbModel(0, 2, 100, 0, FAKE_DEV + (1 << 20))
+    assert lib.nb_model_expand(ctypes.byref(_model(2, 10)), idx, ctypes.byref(out), 0, None) == -1  # untrained
+    assert lib.nb_model_expand(ctypes.byref(km), None, ctypes.byref(out), 0, None) == -1
+    assert lib.nb_model_expand(ctypes.byref(km), idx, None, 0, None) == -1
+    small = _lib.NbModel(0, 2, 5, 0, FAKE_DEV + (1 << 20))
+    assert lib.nb_model_expand(ctypes.byref(km), idx, ctypes.byref(small), 0, None) == -1      # fewer features
+    other = _lib.NbModel(1, 2, 100, 0, FAKE_DEV + (1 << 20))
+    assert lib.nb_model_expand(ctypes.byref(km), idx, ctypes.byref(other), 0, None) == -1      # kind differs
+    same = _lib.NbModel(0, 2, 100, 0, FAKE_DEV)
+    assert lib.nb_model_expand(ctypes.byref(km), idx, ctypes.byref(same), 0, None) == -1       # same buffer
+    g = _lib.NbModel(2, 2, 10, 1, FAKE_DEV)
+    gout = _lib.NbModel(2, 2, 100, 0, FAKE_DEV + (1 << 20))
+    assert lib.nb_model_expand(ctypes.byref(g), idx, ctypes.byref(gout), 0, None) == -1        # Gaussian

@@ -158,6 +158,84 @@ def test_model_on_features_rejects_bad_index():
     assert torch.equal(mk.counts(), m.counts()[:, rep.long()])
 
 
+# ------------------------------------------------------------------ expand
+
+def _padded_rows(X, F):
+    """X [n, F] on rows of whole dwords (the stride training and scoring take)."""
+    if (F * X.element_size()) % 4 == 0:
+        return X
+    Xp = torch.zeros((X.shape[0], (F + 3) // 4 * 4), dtype=X.dtype, device=DEV)
+    Xp[:, :F] = X
+    return Xp[:, :F]
+
+
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+@pytest.mark.parametrize("F,k", [(2000, 200), (1000, 20), (300, 300), (7, 3), (1025, 1)])
+def test_expanded_model_scores_full_rows(kind, F, k):
+    _case(f"expanded model F={F} k={k} {kind}")
+    m, om, X, y, wl = _trained(6, F, 1500, kind)
+    idx = nbg.select_features([m], k)[0].contiguous()
+    mk = nbg.model_on_features(m, idx)
+    me = nbg.expand_model(mk, idx, F)
+    assert me.trained and me.n_features == F
+    ii = idx.long()
+    rest = torch.ones(F, dtype=torch.bool, device=DEV)
+    rest[ii] = False
+    # tables and rows: the k-feature model's at the selected features, zero elsewhere
+    for part in ("counts", "log_theta", "weight") + (("log_1m_theta",) if kind == nb.BERNOULLI else ()):
+        full, small = getattr(me, part)(), getattr(mk, part)()
+        assert torch.equal(full[:, ii], small), part
+        assert not full[:, rest].any(), part
+    for part in ("form_f32", "form_bf16"):
+        full, small = getattr(me, part)(), getattr(mk, part)()
+        assert torch.equal(full[:, ii], small[:, :k]), part
+        assert not full[:, :F][:, rest].any() and not full[:, F:].any(), part
+    for part in ("class_totals", "class_sums", "bias", "form_bias"):
+        assert torch.equal(getattr(me, part)(), getattr(mk, part)()), part
+    ome = select.expanded_model(select.model_on_features(om, to_np(idx)), to_np(idx), F)
+    Xt, _ = wl.test_set(3001, device=DEV)
+    Xt = _padded_rows(Xt, F)
+    for wtype in (nbg.W_F32, nbg.W_BF16):
+        lab, lp, sc = nbg.score(me, Xt, wtype=wtype, scores=True)
+        torch.cuda.synchronize()
+        assert_scores(ome, to_np(Xt), to_np(lab), to_np(lp), to_np(sc), wtype=wtype)
+
+
+def test_expanded_models_in_one_grouped_launch():
+    """Size groups scored on their full rows with expanded k-feature models,
+    one launch, against the oracle; a group without a model takes the next."""
+    _case("expanded models grouped")
+    F, k = 1000, 80
+    ms, oms, wls = [], [], []
+    for g in range(3):
+        m, om, _, _, wl = _trained(10 + g, F, 1200)
+        idx = nbg.select_features([m], k)[0].contiguous()
+        ms.append(nbg.expand_model(nbg.model_on_features(m, idx), idx, F))
+        oms.append(select.expanded_model(select.model_on_features(om, to_np(idx)), to_np(idx), F))
+        wls.append(wl)
+    xs = [wls[g].test_set(n, device=DEV)[0] for g, n in enumerate((777, 2048, 5))]
+    x3 = wls[2].test_set(300, device=DEV)[0]
+    outs = nbg.score_groups(ms, [(0, xs[0]), (1, xs[1]), (None, x3), (2, xs[2])], scores=True)
+    torch.cuda.synchronize()
+    for (lab, lp, sc), x, om in zip(outs, (xs[0], xs[1], x3, xs[2]), (oms[0], oms[1], oms[2], oms[2])):
+        assert_scores(om, to_np(x), to_np(lab), to_np(lp), to_np(sc))
+
+
+def test_expand_rejects_bad_index_lists():
+    _case("expand bad index")
+    m, *_ = _trained(1, 100, 300)
+    idx = torch.tensor([3, 7, 50], dtype=torch.int32, device=DEV)
+    mk = nbg.model_on_features(m, idx)
+    for bad in ([3, 50, 7], [3, 7, 7], [3, 7, 100], [-1, 7, 50]):
+        with pytest.raises(nbg.NBError) as e:
+            nbg.expand_model(mk, torch.tensor(bad, dtype=torch.int32, device=DEV), 100)
+        assert e.value.code == -5, bad
+    with pytest.raises(nbg.NBError):                 # fewer features than the k-feature model
+        nbg.expand_model(mk, idx, 2)
+    me = nbg.expand_model(mk, idx, 60)               # any width that holds the indices
+    assert me.trained and torch.equal(me.counts()[:, idx.long()], mk.counts())
+
+
 # ------------------------------------------------------------------ gather
 
 def _x(dtype, n, F, ld, seed):

@@ -187,6 +187,31 @@ def test_model_on_features_is_training_on_gathered_columns(kind):
             np.testing.assert_allclose(post, want, rtol=1e-9)
 
 
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+def test_expanded_model_scores_full_rows_as_the_k_model_scores_gathered_rows(kind):
+    rng = np.random.default_rng(23)
+    F = 50
+    X = rng.poisson(rng.gamma(0.5, 2.0, size=F), size=(200, F)).astype(np.uint8)
+    X[rng.random(X.shape) < 0.6] = 0
+    y = np.arange(200) % 2
+    m = nb.train(X, y, 2, kind)
+    for k in (1, 9, F):
+        idx = select.select_model_features(m, k)
+        mk = select.model_on_features(m, idx)
+        me = select.expanded_model(mk, idx, F)
+        assert me.n_features == F and (me.Nc == mk.Nc).all()
+        Xt = rng.poisson(1.5, size=(40, F)).astype(np.uint8)
+        want = nb.joint_log_likelihood(mk, select.gather(Xt, idx))
+        np.testing.assert_allclose(nb.joint_log_likelihood(me, Xt), want, rtol=1e-13, atol=1e-12)
+        # the unselected columns do not matter
+        rest = np.setdiff1d(np.arange(F), idx)
+        Xr = Xt.copy()
+        Xr[:, rest] = rng.integers(0, 200, size=(40, rest.size))
+        np.testing.assert_allclose(nb.joint_log_likelihood(me, Xr), want, rtol=1e-13, atol=1e-12)
+    with pytest.raises(ValueError):
+        select.expanded_model(mk, idx[::-1], F)
+
+
 def test_gather_is_column_selection():
     X = np.arange(24).reshape(4, 6)
     assert select.gather(X, [5, 0, 3]).tolist() == [[r[5], r[0], r[3]] for r in X.tolist()]
@@ -201,6 +226,7 @@ def _pins_fail():
         lambda: test_worked_example_k_feature_model(nb.MULTINOMIAL, 2),
         lambda: test_worked_example_k_feature_model(nb.BERNOULLI, 2),
         lambda: test_model_on_features_is_training_on_gathered_columns(nb.MULTINOMIAL),
+        lambda: test_expanded_model_scores_full_rows_as_the_k_model_scores_gathered_rows(nb.BERNOULLI),
         test_presence_model_normalises_by_files,
         test_empty_class_keys_on_the_other_class,
         test_selection_invariants,
@@ -219,6 +245,7 @@ _orig_keys = select.selection_keys
 _orig_top_k = select.top_k
 _orig_sums = select.class_sums
 _orig_model = select.model_on_features
+_orig_expanded = select.expanded_model
 
 
 def _unnormalised_keys(counts, sums):
@@ -261,6 +288,20 @@ def _full_normaliser_kept(m, idx):
     return mk
 
 
+def _expanded_one_off(mk, idx, F):
+    # tables written one feature to the right of their own column
+    return _orig_expanded(mk, np.minimum(np.asarray(idx) + 1, F - 1) if idx[-1] < F - 1 else idx, F)
+
+
+def _expanded_unselected_presence_kept(mk, idx, F):
+    # the presence model's log(1 - theta) left at log 1/2 outside the selection
+    me = _orig_expanded(mk, idx, F)
+    if me.log_1m_theta is not None:
+        rest = np.setdiff1d(np.arange(F), np.asarray(idx))
+        me.log_1m_theta[:, rest] = np.log(0.5)
+    return me
+
+
 SELECT_MUTATIONS = {
     "difference not normalised": ("selection_keys", _unnormalised_keys),
     "signed difference": ("selection_keys", _signed_keys),
@@ -269,6 +310,8 @@ SELECT_MUTATIONS = {
     "list in rank order, not feature order": ("top_k", _rank_order_output),
     "presence normalised by presence sum": ("class_sums", _presence_by_sum),
     "k-feature model keeps the full normaliser": ("model_on_features", _full_normaliser_kept),
+    "expanded tables one column off": ("expanded_model", _expanded_one_off),
+    "expanded presence model scores unselected absences": ("expanded_model", _expanded_unselected_presence_kept),
 }
 
 

@@ -136,6 +136,20 @@ def oracle_all_cores(wl, Xtr, ytr, Xte, seconds: float):
             "sample": f"the full step x {reps} repetitions, numpy FP64, BLAS with {threads} threads, {sec:.1f} s"}
 
 
+def host_cpu() -> dict:
+    """The host processor the CPU figures were taken on."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": name, "cpus_available": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(wl, Xtr, ytr, Xte, seconds: float):
     """The oracle as it stands, single-threaded (the paper's sequential
     program), on the same step: train on the 200,000 files, score the
@@ -153,7 +167,8 @@ def cpu_baseline(wl, Xtr, ytr, Xte, seconds: float):
             reps += 1
     return {"value": reps * xte.shape[0] / sec, "unit": "files/s", "cores": 1, "kind": "oracle",
             "sample": f"the full step (train {xtr.shape[0]} + score {xte.shape[0]} files) x {reps} repetitions, "
-                      f"numpy FP64, one thread, {sec:.1f} s"}
+                      f"numpy FP64, one thread, {sec:.1f} s",
+            "host": host_cpu()}
 
 
 def f_sweep(nbg, W):

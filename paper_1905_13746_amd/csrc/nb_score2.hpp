@@ -130,8 +130,12 @@ __device__ __forceinline__ void finish_block(const Score2Args& a, float (&acc)[k
       const int h = cnt / 2;
 #pragma unroll
       for (int k = 0; k < h; ++k) {
-        const float send = up ? val[k] : val[k + h];
-        const float keep = up ? val[k + h] : val[k];
+        // both values loaded first: a conditional over the array elements
+        // themselves selects an address, i.e. a runtime index into val,
+        // which the compiler expands into a compare/select chain over all V
+        const float lo = val[k], hi = val[k + h];
+        const float send = up ? lo : hi;
+        const float keep = up ? hi : lo;
         val[k] = keep + __shfl_xor(send, m);
       }
       if (up) offset += h;

@@ -15,6 +15,11 @@ the source it was taken on).
 
 prints per-kernel dispatch counts and mean/min/max durations from a
 `--kernel-trace` database.
+
+    python -m paper_1905_13746_amd.rocprof_summary counters DIR [SUBSTRING]
+
+prints, per kernel, the mean per dispatch of every counter a `--pmc` run
+collected (values summed over the counter's instances per dispatch).
 """
 from __future__ import annotations
 
@@ -91,6 +96,21 @@ def stats(a):
         print(f"{len(ds):6d}  mean {sum(ds) / len(ds):10.2f} us  min {min(ds):10.2f}  max {max(ds):10.2f}  {name[:110]}")
 
 
+def counters(a):
+    c = _db(a.dir)
+    per = {}
+    for name, cn, val, disp in c.execute(
+            "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        if a.kernel and a.kernel not in name:
+            continue
+        d = per.setdefault(name, {}).setdefault(cn, {})
+        d[disp] = d.get(disp, 0.0) + float(val)
+    for name, cs in sorted(per.items()):
+        print(name[:140])
+        for cn, ds in sorted(cs.items()):
+            print(f"    {cn:32s} {sum(ds.values()) / len(ds):20.1f}   ({len(ds)} dispatches)")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -108,8 +128,11 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("dir")
     s.add_argument("kernel", nargs="?", default="")
+    k = sub.add_parser("counters")
+    k.add_argument("dir")
+    k.add_argument("kernel", nargs="?", default="")
     a = ap.parse_args(argv)
-    (traffic if a.cmd == "traffic" else stats)(a)
+    {"traffic": traffic, "stats": stats, "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

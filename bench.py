@@ -541,18 +541,25 @@ def serve_leg(nbg, W, n_requests: int = 8000, full: bool = False):
                        "1 GiB arena"}
     fracs = (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2) if full else (0.25, 0.5, 0.9)
     fixed = (1_000, 3_000, 10_000, 30_000, 100_000) if full else ()
+    def progress(mode, key, r):
+        print(f"[serve] {mode} {key}: {r['req_per_s']:.0f} req/s, p50 {r['p50_ms']:.3f} ms, "
+              f"p99 {r['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
+
     for mode, dev in (("host_inputs", False), ("device_inputs", True)):
         sat = run(*trace(float("inf")), dev)
+        progress(mode, "saturation", sat)
         res = {"saturation": sat}
         for frac in fracs:
             qps = frac * sat["req_per_s"]
             r = run(*trace(qps), dev)
             r["offered_req_per_s"] = qps
             res[f"load_{frac}"] = r
+            progress(mode, f"load_{frac}", r)
         for qps in fixed:
             r = run(*trace(float(qps)), dev)
             r["offered_req_per_s"] = qps
             res[f"rate_{qps}"] = r
+            progress(mode, f"rate_{qps}", r)
         out[mode] = res
     return out
 

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
   constexpr int NV = EB;
   constexpr int G = 64 / LPR;
-  constexpr int R = kRowSteps;
+  constexpr int R = row_steps<XT, false>();
   constexpr int BR = G * R;
   constexpr int CW = 16 * LPR;
   constexpr int TPL = kStreamTPL;
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
 template <int XT, int LPR, int NS, bool BIN, bool MULTI>
 __global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsArgs g) {
   extern __shared__ float tbl[];        // [NS][Fp] of the current group
-  __shared__ float stage[kWaves][NS][(64 / LPR) * kRowSteps];
+  __shared__ float stage[kWaves][NS][(64 / LPR) * row_steps<XT, false>()];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t B = g.total_blocks;
   int64_t b = B * blockIdx.x / gridDim.x;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsAr
 template <int XT, int LPR, int NS, bool BIN, bool MULTI>
 __global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g) {
   extern __shared__ float tbl[];        // [NS][Fp] of the current item's group
-  __shared__ float stage[kWaves][NS][(64 / LPR) * kRowSteps];
+  __shared__ float stage[kWaves][NS][(64 / LPR) * row_steps<XT, false>()];
   __shared__ int32_t s_item;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (;;) {
@@ -390,7 +390,7 @@ int setup_groups(const nb_model* models, int32_t n_models, const nb_group* group
   S->descs.resize(n_groups);
   S->blocks.assign(n_groups, 0);
   S->lpr = lanes_per_row(S->F);
-  const int64_t br = (int64_t)(64 / S->lpr) * kRowSteps;
+  const int64_t br = (int64_t)(64 / S->lpr) * row_steps_of(xtype, false);
   for (int32_t g = 0; g < n_groups; ++g) {
     const nb_group& G = groups[g];
     const nb_model* m = &models[groups[route[g]].model];
@@ -455,7 +455,7 @@ int default_tile_blocks(const GroupSetup& S) {
 }
 
 int tile_blocks_from_rows(const GroupSetup& S, int32_t tile_rows) {
-  const int br = (64 / S.lpr) * kRowSteps;
+  const int br = (64 / S.lpr) * row_steps_of(S.xtype, false);
   const int64_t b = ((int64_t)tile_rows + br - 1) / br;
   return (int)std::max<int64_t>(kWaves, (b + kWaves - 1) / kWaves * kWaves);
 }
@@ -945,7 +945,7 @@ int nb_group_plan_launch(nb_group_plan* plan, void* stream) {
 
 int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out) {
   if (!plan || !out) return fail(NB_EINVAL, "NULL argument");
-  const int br = (64 / plan->S.lpr) * kRowSteps;
+  const int br = (64 / plan->S.lpr) * row_steps_of(plan->S.xtype, false);
   const LaunchDesc L = describe(plan->S, plan->w);
   const int code = plan->w.code;
   out->schedule = code == 0 ? NB_SCHEDULE_STATIC : (code > 0 ? NB_SCHEDULE_DYNAMIC : NB_SCHEDULE_STREAM);

@@ -15,8 +15,9 @@
 // smallest power of two >= F/16, at most 64), each lane owning 16 consecutive
 // features per chunk of 16*LPR features: its loads are 16 contiguous bytes,
 // so a wave instruction reads 64/LPR whole rows (or one 16*LPR-feature
-// stretch of a row) contiguously.  A wave processes R = 8 row-steps of
-// 64/LPR rows per block and strides over blocks (persistent grid sized to the
+// stretch of a row) contiguously.  A wave processes R row-steps of
+// 64/LPR rows per block (R = 16 for byte features; 8 for int32 features and
+// the Gaussian kernel) and strides over blocks (persistent grid sized to the
 // resident capacity).  The table row(s) sit in LDS as FP32 (BF16 tables are
 // widened on load: exact).  Lane partial sums are reduced across the LPR
 // lanes with a transposed butterfly (each exchange step halves the number of
@@ -34,11 +35,11 @@ namespace {
 template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false>
 __global__ __launch_bounds__(kThreads) void score2_kernel(Score2Args a) {
   extern __shared__ float tbl[];        // [NS][Fp] (Gaussian: [4][Fp], means then h)
-  __shared__ float stage[kWaves][NS][(64 / LPR) * kRowSteps];
+  __shared__ float stage[kWaves][NS][(64 / LPR) * row_steps<XT, QUAD>()];
   if constexpr (QUAD) stage_table_q(a, tbl);
   else stage_table<NS>(a, tbl);
   __syncthreads();
-  constexpr int BR = (64 / LPR) * kRowSteps;
+  constexpr int BR = (64 / LPR) * row_steps<XT, QUAD>();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wave_id = (int64_t)blockIdx.x * kWaves + wave;
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
@@ -84,7 +85,7 @@ int launch_score2(const nb_model* m, const nb_layout& L, const void* x, int32_t 
   const void* fn = quad ? pick_quad(xtype, lpr, a.nch > 1, ns)
                         : pick_score2<Single>(xtype, lpr, a.nch > 1, ns, m->kind == NB_BERNOULLI);
   if (lds > 64 * 1024) NB_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int64_t rows_per_blk = (int64_t)(64 / lpr) * kRowSteps;
+  const int64_t rows_per_blk = (int64_t)(64 / lpr) * row_steps_of(xtype, quad);
   const int64_t nblk = (n + rows_per_blk - 1) / rows_per_blk;
   const int64_t want = (nblk + kWaves - 1) / kWaves;
   const int64_t cap = (int64_t)resident_per_cu(fn, kThreads, lds) * device_cu_count();

@@ -19,17 +19,31 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-// Rows per lane group per block, and whether a wave double-buffers its loads
-// (the next unit's loads in flight while the current one is accumulated).
+// Row-steps per block (a block is R row-steps of 64/LPR rows): 16 for the
+// linear kernels on byte features (multinomial, Bernoulli; uint8 or FP8), 8
+// for int32 features (four 16-byte vectors per lane and row: 16 row-steps,
+// double-buffered, would not fit the register file) and for the Gaussian
+// kernel (four table rows and a longer chain per feature); measured on
+// gfx950 at every lanes-per-file width.  And whether a wave double-buffers
+// its loads (the next unit's loads in flight while the current one is
+// accumulated).
 #ifndef NB_ROW_STEPS
-#define NB_ROW_STEPS 8
+#define NB_ROW_STEPS 16
+#endif
+#ifndef NB_ROW_STEPS_HEAVY
+#define NB_ROW_STEPS_HEAVY 8
 #endif
 #ifndef NB_PIPELINE
 #define NB_PIPELINE 1
 #endif
-constexpr int kRowSteps = NB_ROW_STEPS;
+template <int XT, bool QUAD>
+constexpr int row_steps() { return (QUAD || XT == NB_X_I32) ? NB_ROW_STEPS_HEAVY : NB_ROW_STEPS; }
+inline int row_steps_of(int xtype, bool quad) {
+  return (quad || xtype == NB_X_I32) ? NB_ROW_STEPS_HEAVY : NB_ROW_STEPS;
+}
 // the transposed butterfly of finish_block halves R x NS values per step
-static_assert((kRowSteps & (kRowSteps - 1)) == 0, "row steps per block must be a power of two");
+static_assert((NB_ROW_STEPS & (NB_ROW_STEPS - 1)) == 0 && (NB_ROW_STEPS_HEAVY & (NB_ROW_STEPS_HEAVY - 1)) == 0,
+              "row steps per block must be powers of two");
 constexpr bool kPipeline = NB_PIPELINE != 0;
 
 struct Score2Args {
@@ -107,12 +121,11 @@ __device__ float2 g_sink_pair[64];
 // butterfly), stage the per-row totals in LDS and run the fused epilogue for
 // the block's rows [row0, row0 + nrows).  FAST: nrows == BR and no branches
 // around the stores (lanes beyond BR repeat a row: same value, same address).
-template <int LPR, int NS, bool FAST>
-__device__ __forceinline__ void finish_block(const Score2Args& a, float (&acc)[kRowSteps][NS], int lane, int wave,
+template <int LPR, int NS, bool FAST, int R>
+__device__ __forceinline__ void finish_block(const Score2Args& a, float (&acc)[R][NS], int lane, int wave,
                                              int sub, const float (&rb)[NS], int64_t row0, int nrows,
-                                             float (*stage)[NS][(64 / LPR) * kRowSteps]) {
+                                             float (*stage)[NS][(64 / LPR) * R]) {
   constexpr int G = 64 / LPR;
-  constexpr int R = kRowSteps;
   constexpr int BR = G * R;
   constexpr int V = R * NS;
   float val[V];
@@ -219,12 +232,11 @@ __device__ __forceinline__ void fp8_keep_mask(int F, int fc, uint32_t (&keep)[4]
   }
 }
 
-template <int XT, int NS, bool BIN, int NV>
-__device__ __forceinline__ void accumulate_rows(dev::u32x4 (&v)[kRowSteps][NV], const float (&w)[NS][16],
-                                                const uint32_t (&keep)[4], bool masked,
-                                                float (&acc)[kRowSteps][NS]) {
+template <int XT, int NS, bool BIN, int NV, int R>
+__device__ __forceinline__ void accumulate_rows(dev::u32x4 (&v)[R][NV], const float (&w)[NS][16],
+                                                const uint32_t (&keep)[4], bool masked, float (&acc)[R][NS]) {
 #pragma unroll
-  for (int i = 0; i < kRowSteps; ++i) {
+  for (int i = 0; i < R; ++i) {
     if (XT == NB_X_FP8 && masked) {
 #pragma unroll
       for (int d = 0; d < 4; ++d) v[i][0][d] &= keep[d];
@@ -275,11 +287,11 @@ __device__ __forceinline__ void accumulate_seg_q(const dev::u32x4 (&v)[(XT == NB
   }
 }
 
-template <int XT, int NS, int NV>
-__device__ __forceinline__ void accumulate_rows_q(dev::u32x4 (&v)[kRowSteps][NV], const float (&mu)[2][16],
-                                                  const float (&h)[2][16], float (&acc)[kRowSteps][NS]) {
+template <int XT, int NS, int NV, int R>
+__device__ __forceinline__ void accumulate_rows_q(dev::u32x4 (&v)[R][NV], const float (&mu)[2][16],
+                                                  const float (&h)[2][16], float (&acc)[R][NS]) {
 #pragma unroll
-  for (int i = 0; i < kRowSteps; ++i) accumulate_seg_q<XT, NS>(v[i], mu, h, acc[i]);
+  for (int i = 0; i < R; ++i) accumulate_seg_q<XT, NS>(v[i], mu, h, acc[i]);
 }
 
 // Copy the NS scoring rows (FP32, or BF16 widened: exact) into LDS.  The
@@ -307,11 +319,11 @@ __device__ __forceinline__ void stage_table_q(const Score2Args& a, float* tbl) {
 // QUAD: a Gaussian model (x and x^2 rows, see accumulate_seg_q).
 template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false>
 __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* tbl, int64_t first, int64_t stride,
-                                             int64_t end, float (*stage)[NS][(64 / LPR) * kRowSteps]) {
+                                             int64_t end, float (*stage)[NS][(64 / LPR) * row_steps<XT, QUAD>()]) {
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
   constexpr int NV = EB;
   constexpr int G = 64 / LPR;           // rows per row-step
-  constexpr int R = kRowSteps;
+  constexpr int R = row_steps<XT, QUAD>();
   constexpr int BR = G * R;             // rows per block
   constexpr int CW = 16 * LPR;          // features per chunk
 
@@ -501,7 +513,7 @@ int make_score2_args(const nb_model* m, const nb_layout& L, const void* x, int32
   a.Fp = L.padded_features;
   a.nch = nch;
   a.wt = wtype;
-  const int64_t rows_per_blk = (int64_t)(64 / lpr) * kRowSteps;
+  const int64_t rows_per_blk = (int64_t)(64 / lpr) * row_steps_of(xtype, quad);
   if (rows_per_blk * a.ld_bytes >= (int64_t)1 << 31)
     return fail(NB_EINVAL, "row stride too large (a block of rows must span < 2 GiB)");
   // leading blocks whose rows all exist and whose loads stay inside the buffer

@@ -238,6 +238,9 @@ int launch_scoreC_valu(const nb_model* m, const nb_layout& L, const void* x, int
   ScoreCArgs a;
   a.x = static_cast<const uint8_t*>(x);
   a.ld_bytes = ld * eb;
+  // a wave stages 64 rows through one buffer resource with 32-bit offsets
+  if ((int64_t)64 * a.ld_bytes >= ((int64_t)1 << 31))
+    return fail(NB_EINVAL, "row stride too large (64 rows must span < 2 GiB)");
   a.n = n;
   a.total_bytes = ((n - 1) * ld + m->n_features) * (int64_t)eb;
   a.rows32 = reinterpret_cast<const float*>(base + L.off_form_f32);

@@ -99,6 +99,17 @@ def test_score_argument_errors(lib, kw, code):
     assert _score(lib, _model(), **kw) == code
 
 
+def test_score_rejects_strides_beyond_the_staging_range(lib):
+    """Every scoring path stages a group of rows through one buffer resource
+    with 32-bit offsets: strides whose group spans 2 GiB are refused before
+    anything is launched."""
+    for C, wt, xtype in ((3, 0, 0), (2, 0, 0), (16, 1, 0), (3, 0, 1)):
+        eb = 4 if xtype == 1 else 1
+        ld = (1 << 25) // eb
+        assert _score(lib, _model(C=C), ld=ld, wt=wt, xtype=xtype) == -1, (C, wt, xtype)
+        assert b"stride" in lib.nb_last_error(), (C, wt, xtype)
+
+
 def test_score_empty_batch_is_noop(lib):
     assert _score(lib, _model(), n=0, x=None) == 0
 

@@ -221,8 +221,10 @@ int nb_model_select(const nb_model* full, const int32_t* idx, int32_t k, double 
                     void* workspace, size_t workspace_bytes, int32_t flags, void* stream);
 
 /* The k-feature model widened to the full feature vector: out scores a
- * file's full F-feature row exactly as km scores its k selected features
- * (section 4: each group classifies with its own top-k features), so the
+ * file's full F-feature row with the same terms as km scores its k selected
+ * features (the summation order follows the full width, so sums agree to
+ * rounding, not bit for bit) (section 4: each group classifies with its own
+ * top-k features), so the
  * scoring kernels read each full row once instead of a gather writing and
  * re-reading the k selected bytes.  out's weights, log tables, counts and
  * scoring rows are km's at the features idx[j] and zero elsewhere; its
@@ -231,8 +233,9 @@ int nb_model_select(const nb_model* full, const int32_t* idx, int32_t k, double 
  * km: trained, multinomial or Bernoulli, k = km->n_features features.
  * idx: device int32[k], strictly ascending, in [0, n_features) (as
  * nb_select_features writes them); otherwise the call fails with NB_EDATA
- * (device check).  out: kind and n_classes of km, n_features >= k, its own
- * buffer.  Synchronises `stream` and returns the outcome unless flags holds
+ * (device check); read while the call's kernels run (keep it alive until
+ * the stream has passed them).  out: kind and n_classes of km,
+ * n_features >= k, its own buffer, not overlapping km's.  Synchronises `stream` and returns the outcome unless flags holds
  * NB_TRAIN_ASYNC (then nb_model_status() reports it).
  * Errors: NB_EINVAL, NB_EDATA. */
 int nb_model_expand(const nb_model* km, const int32_t* idx, nb_model* out, int32_t flags, void* stream);

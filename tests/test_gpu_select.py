@@ -201,14 +201,15 @@ def test_expanded_model_scores_full_rows(kind, F, k):
         assert_scores(ome, to_np(Xt), to_np(lab), to_np(lp), to_np(sc), wtype=wtype)
 
 
-def test_expanded_models_in_one_grouped_launch():
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+def test_expanded_models_in_one_grouped_launch(kind):
     """Size groups scored on their full rows with expanded k-feature models,
     one launch, against the oracle; a group without a model takes the next."""
-    _case("expanded models grouped")
+    _case(f"expanded models grouped {kind}")
     F, k = 1000, 80
     ms, oms, wls = [], [], []
     for g in range(3):
-        m, om, _, _, wl = _trained(10 + g, F, 1200)
+        m, om, _, _, wl = _trained(10 + g, F, 1200, kind)
         idx = nbg.select_features([m], k)[0].contiguous()
         ms.append(nbg.expand_model(nbg.model_on_features(m, idx), idx, F))
         oms.append(select.expanded_model(select.model_on_features(om, to_np(idx)), to_np(idx), F))

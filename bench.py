@@ -487,10 +487,38 @@ def gaussian_leg(nbg, W, F: int = 1000, n_train: int = 200_000, n_test: int = 1_
     ms = timed(lambda: nbg.score(m, Xt, out=(lab, lp, None)), steps)
     ms_mn = timed(lambda: nbg.score(mm, Xt, out=(lab, lp, None)), steps)
     gbs = n_test * (F + 12) / (ms / 1e3) / 1e9
+    cpu = None if fill else gaussian_cpu_baseline(X[:n_train // 10], y[:n_train // 10], Xt[:n_test // 10],
+                                                  n_train, n_test)
     return {"workload": f"two-class Gaussian NB, F={F} uint8 counts, train {n_train} + score {n_test} files",
+            "cpu_baseline": cpu,
             "score_ms": ms, "score_files_per_s": n_test / (ms / 1e3), "score_GBps": gbs,
             "score_frac_of_peak": gbs / HBM_PEAK_GBPS, "multinomial_score_ms": ms_mn,
-            "train_ms": ms_train, "multinomial_train_ms": ms_train_mn}
+            "train_ms": ms_train, "multinomial_train_ms": ms_train_mn,
+            "step_files_per_s": n_test / ((ms + ms_train) / 1e3)}
+
+
+def gaussian_cpu_baseline(Xs, ys, Xts, n_train: int, n_test: int, seconds: float = 5.0):
+    """The oracle's Gaussian training and classification, one thread, on a
+    tenth of the leg's files, scaled linearly to the full step (both passes
+    are linear in the number of files)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import nb
+    xtr, ytr, xte = Xs.cpu().numpy(), ys.cpu().numpy(), Xts.cpu().numpy()
+    reps, t_tr, t_sc = 0, 0.0, 0.0
+    with threadpool_limits(limits=1):
+        while t_tr + t_sc < seconds and reps < 10:
+            t0 = time.perf_counter()
+            om = nb.train(xtr, ytr, 2, nb.GAUSSIAN)
+            t1 = time.perf_counter()
+            nb.classify(om, xte)
+            t2 = time.perf_counter()
+            t_tr += t1 - t0
+            t_sc += t2 - t1
+            reps += 1
+    step_s = (t_tr / reps) * (n_train / xtr.shape[0]) + (t_sc / reps) * (n_test / xte.shape[0])
+    return {"value": n_test / step_s, "unit": "files/s", "cores": 1, "kind": "oracle",
+            "sample": f"train on {xtr.shape[0]} + classify {xte.shape[0]} files x {reps}, numpy FP64, one "
+                      f"thread, {t_tr + t_sc:.1f} s; scaled to the step of {n_train} + {n_test} files"}
 
 
 def serve_leg(nbg, W, n_requests: int = 8000, full: bool = False):

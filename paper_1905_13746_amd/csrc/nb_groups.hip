@@ -101,6 +101,7 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
   constexpr int BR = G * R;
   constexpr int CW = 16 * LPR;
   constexpr int TPL = kStreamTPL;
+  using LM = LaneMap<XT, LPR>;
   __shared__ __attribute__((aligned(16))) float tbl2[2][kStreamTable];
   __shared__ __attribute__((aligned(16))) float tbl_sink[kStreamTable];
   __shared__ float stage[kWaves][NS][BR];
@@ -134,7 +135,8 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
     uint32_t voff[R];
     auto set_voff = [&](int64_t ld) {
 #pragma unroll
-      for (int i = 0; i < R; ++i) voff[i] = (uint32_t)((i * G + sub) * ld) + (uint32_t)(16 * j * EB);
+      for (int i = 0; i < R; ++i)
+        voff[i] = (uint32_t)((i * G + sub) * ld) + (uint32_t)((XT == NB_X_I32) ? 16 * j : 16 * j * EB);
     };
     set_voff(ia.ld_bytes);
     auto advance = [&]() {
@@ -170,12 +172,22 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
       const uint32_t toff = (uint32_t)threadIdx.x * TPL * (bf ? 2u : 4u);
       tdst[0] = dev::buffer_load16(trs, toff);
       tdst[1] = dev::buffer_load16(trs, bf ? (uint32_t)tbytes : toff + 16u);
-      // lanes whose 16 features of this chunk lie past F read nothing
-      const bool live = ich * CW + 16 * j < ia.F;
+      // loads whose features of this chunk lie past F read nothing
+      if constexpr (XT == NB_X_I32) {
 #pragma unroll
-      for (int i = 0; i < R; ++i)
+        for (int q = 0; q < NV; ++q) {
+          const bool live = ich * CW + LM::feat0(j) + q * LM::kWStep < ia.F;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + 16 * q : dev::kNoAccess);
+          for (int i = 0; i < R; ++i)
+            dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + q * LM::kLoadStep : dev::kNoAccess);
+        }
+      } else {
+        const bool live = ich * CW + 16 * j < ia.F;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + 16 * q : dev::kNoAccess);
+      }
       __builtin_amdgcn_sched_barrier(0);
       advance();
     };
@@ -210,13 +222,13 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
 #pragma unroll
         for (int s = 0; s < NS; ++s) rb[s] = dev::load_uniform(ca.row_bias + s);
         if (!MULTI) {
-          load_table<XT, NS>(tb, Fp, 16 * j, w);
+          load_table<XT, NS, LM::kWStep>(tb, Fp, (XT == NB_X_I32) ? LM::feat0(j) : 16 * j, w);
           if (XT == NB_X_FP8) fp8_keep_mask(ca.F, 16 * j, keep);
         }
       }
       if (MULTI) {
-        const int fc = cch * CW + 16 * j;
-        load_table<XT, NS>(tb, Fp, fc, w);
+        const int fc = cch * CW + ((XT == NB_X_I32) ? LM::feat0(j) : 16 * j);
+        load_table<XT, NS, LM::kWStep>(tb, Fp, fc, w);
         if (XT == NB_X_FP8) fp8_keep_mask(ca.F, fc, keep);
       }
       accumulate_rows<XT, NS, BIN, NV>(src, w, keep, true, acc);

@@ -206,14 +206,27 @@ __device__ __forceinline__ void finish_block(const Score2Args& a, float (&acc)[R
   wave_lds_sync();
 }
 
-template <int XT, int NS>
+// Where a lane's features sit inside a chunk of 16*LPR features.  Byte
+// features: 16 consecutive features from byte 16j, one 16-byte load.  int32
+// features: four 16-byte loads 16*LPR bytes apart, so load q of the wave
+// reads one contiguous 16*LPR-byte stretch of the chunk (whole cache lines
+// per instruction); lane j holds features 4*LPR*q + 4j .. 4*LPR*q + 4j + 3.
+template <int XT, int LPR>
+struct LaneMap {
+  static constexpr int kLoadStep = (XT == NB_X_I32) ? 16 * LPR : 16;   // bytes between a lane's loads
+  static constexpr int kWStep = (XT == NB_X_I32) ? 4 * LPR : 4;        // features between its groups of four
+  static __device__ __forceinline__ int feat0(int j) { return (XT == NB_X_I32) ? 4 * j : 16 * j; }
+};
+
+// The lane's 16 weights per row: four groups of four features, WSTEP apart.
+template <int XT, int NS, int WSTEP = 4>
 __device__ __forceinline__ void load_table(const float* tbl, int Fp, int fc, float (&w)[NS][16]) {
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const float4* t4 = reinterpret_cast<const float4*>(tbl + s * Fp + fc);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float4 t = t4[q];
+      const float4 t = t4[q * (WSTEP / 4)];
       w[s][4 * q + 0] = t.x;
       w[s][4 * q + 1] = t.y;
       w[s][4 * q + 2] = t.z;
@@ -251,11 +264,11 @@ __device__ __forceinline__ void accumulate_rows(dev::u32x4 (&v)[R][NV], const fl
 // h_0, h_1; acc[0] gathers the log-odds terms h_1 d_1^2 - h_0 d_0^2 and,
 // with raw scores, acc[1] the terms h_0 d_0^2 of s_0, so the reduction and
 // the epilogue are those of the linear kinds.
-template <int XT>
+template <int XT, int WSTEP = 4>
 __device__ __forceinline__ void load_table_q(const float* tbl, int Fp, int fc, float (&mu)[2][16],
                                              float (&h)[2][16]) {
-  load_table<XT, 2>(tbl, Fp, fc, mu);
-  load_table<XT, 2>(tbl + 2 * Fp, Fp, fc, h);
+  load_table<XT, 2, WSTEP>(tbl, Fp, fc, mu);
+  load_table<XT, 2, WSTEP>(tbl + 2 * Fp, Fp, fc, h);
 }
 
 template <int XT, int NS>
@@ -326,16 +339,18 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
   constexpr int R = row_steps<XT, QUAD>();
   constexpr int BR = G * R;             // rows per block
   constexpr int CW = 16 * LPR;          // features per chunk
+  using LM = LaneMap<XT, LPR>;
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = lane / LPR, j = lane % LPR;
   const int nch = MULTI ? a.nch : 1;
   const int64_t ld = a.ld_bytes;
-  // this lane's byte offsets inside a block: row (i*G + sub), feature 16*j
+  // this lane's first byte offsets inside a block: row (i*G + sub), byte 16*j
   uint32_t voff[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) voff[i] = (uint32_t)((i * G + sub) * ld) + (uint32_t)(16 * j * EB);
+  for (int i = 0; i < R; ++i)
+    voff[i] = (uint32_t)((i * G + sub) * ld) + (uint32_t)((XT == NB_X_I32) ? 16 * j : 16 * j * EB);
 
   float rb[NS];
 #pragma unroll
@@ -345,11 +360,11 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
   float w2[QUAD ? 2 : 1][16];        // Gaussian: h
   uint32_t keep[4] = {~0u, ~0u, ~0u, ~0u};
   auto load_w = [&](int fc) {
-    if constexpr (QUAD) load_table_q<XT>(tbl, a.Fp, fc, w, w2);
-    else load_table<XT, NS>(tbl, a.Fp, fc, w);
+    if constexpr (QUAD) load_table_q<XT, LM::kWStep>(tbl, a.Fp, fc, w, w2);
+    else load_table<XT, NS, LM::kWStep>(tbl, a.Fp, fc, w);
   };
   if (!MULTI) {
-    load_w(16 * j);
+    load_w((XT == NB_X_I32) ? LM::feat0(j) : 16 * j);
     if (XT == NB_X_FP8) fp8_keep_mask(a.F, 16 * j, keep);
   }
 
@@ -383,13 +398,23 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
     const int64_t blk = first + (int64_t)ib * stride;
     const int64_t off = blk * BR * ld + (int64_t)ich * CW * EB;
     const auto rsrc = dev::make_rsrc(a.x + off, a.total_bytes - off);
-    // a lane whose 16 features of this chunk all lie past F reads nothing:
+    // a load whose features of this chunk all lie past F reads nothing:
     // those bytes belong to the next row, which its own loads fetch
-    const bool live = ich * CW + 16 * j < a.F;
+    if constexpr (XT == NB_X_I32) {
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+      for (int q = 0; q < NV; ++q) {
+        const bool live = ich * CW + LM::feat0(j) + q * LM::kWStep < a.F;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + 16 * q : dev::kNoAccess);
+        for (int i = 0; i < R; ++i)
+          dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + q * LM::kLoadStep : dev::kNoAccess);
+      }
+    } else {
+      const bool live = ich * CW + 16 * j < a.F;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dst[i][q] = dev::buffer_load16(rsrc, live ? voff[i] + 16 * q : dev::kNoAccess);
+    }
     // keep the loads here: the scheduler would otherwise sink them into the
     // arithmetic of the unit being consumed and shrink the overlap
     __builtin_amdgcn_sched_barrier(0);
@@ -402,7 +427,7 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
   int cch = 0;      // chunk being computed
   auto consume = [&](dev::u32x4 (&src)[R][NV]) {
     if (MULTI) {
-      const int fc = cch * CW + 16 * j;
+      const int fc = cch * CW + ((XT == NB_X_I32) ? LM::feat0(j) : 16 * j);
       load_w(fc);
       if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
     }
@@ -444,7 +469,7 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
     const int64_t row0 = blk * BR;
     const int nrows = (int)min((int64_t)BR, nrows_total - row0);
     for (int ch = 0; ch < nch; ++ch) {
-      const int fc = ch * CW + 16 * j;
+      const int fc = ch * CW + ((XT == NB_X_I32) ? LM::feat0(j) : 16 * j);
       if (MULTI) {
         load_w(fc);
         if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
@@ -456,10 +481,17 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
 #pragma unroll
         for (int q = 0; q < NV; ++q) v[i][q] = dev::u32x4{0u, 0u, 0u, 0u};
         if (L < nrows) {
-          const int64_t off = (row0 + L) * ld + (int64_t)fc * EB;
+          if constexpr (XT == NB_X_I32) {
+            const int64_t off = (row0 + L) * ld + (int64_t)ch * CW * EB + 16 * j;
 #pragma unroll
-          for (int q = 0; q < NV; ++q)
-            v[i][q] = dev::load16_guarded(a.x + off + 16 * q, a.total_bytes - off - 16 * q);
+            for (int q = 0; q < NV; ++q)
+              v[i][q] = dev::load16_guarded(a.x + off + q * LM::kLoadStep, a.total_bytes - off - q * LM::kLoadStep);
+          } else {
+            const int64_t off = (row0 + L) * ld + (int64_t)fc * EB;
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+              v[i][q] = dev::load16_guarded(a.x + off + 16 * q, a.total_bytes - off - 16 * q);
+          }
         }
       }
       accumulate(v);

@@ -15,7 +15,8 @@ label + 2 x 4-byte log posteriors per file) over its average launch duration,
 measured with HIP events on the launch stream.  `cpu_baseline` times the FP64
 oracle on the host (one thread, the paper's sequential program) on the same
 step's inputs.  Extra objects (skip with --no-extras):
-  f_sweep    scoring bandwidth of the two-class kernel at F = 100, 500, 5000
+  f_sweep    scoring bandwidth of the two-class kernel at F = 100, 500, 5000, and
+             of the int32-feature variant at F = 1000
   precision  16 classes, F = 4096, 4,000,000 files: the plain FP32 vector path
              vs the BF16 table on the matrix cores (uint8 and FP8 features),
              with the labels of the paths compared on every file.
@@ -189,6 +190,23 @@ def f_sweep(nbg, W):
                        "frac_of_peak": gbs / HBM_PEAK_GBPS}
         del Xt, lab, lp
         torch.cuda.empty_cache()
+    # the int32-feature variant of the F = 1000 workload (4 bytes per feature)
+    F, n = 1000, 1_000_000
+    wl = W.binary_u8(F)
+    X, y = wl.train_set(100_000, device="cuda")
+    X = X.to(torch.int32)
+    m = nbg.Model(2, F, "multinomial")
+    nbg.train(m, X, y)
+    del X, y
+    Xt = wl.test_set(n, device="cuda")[0].to(torch.int32)
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    lp = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    ms = timed(lambda: nbg.score(m, Xt, out=(lab, lp, None)))
+    gbs = n * (4 * F + 12) / (ms / 1e3) / 1e9
+    out["1000_int32"] = {"n_files": n, "ms": ms, "files_per_s": n / (ms / 1e3), "GBps": gbs,
+                         "frac_of_peak": gbs / HBM_PEAK_GBPS}
+    del Xt, lab, lp
+    torch.cuda.empty_cache()
     return out
 
 

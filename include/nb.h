@@ -19,6 +19,14 @@
  *     (n - 1) * ld + F elements.  Features are non-negative occurrence counts
  *     (the paper's per-file opcode occurrences, section 3); scoring does not
  *     re-validate them.
+ *   - Alignment of feature matrices (nb_train, nb_score, nb_score_groups,
+ *     nb_serve): x must be 4-byte aligned and the row stride ld * element
+ *     size a multiple of 4 bytes, since every row is read with dword-aligned
+ *     vector loads.  A byte matrix whose F is not a multiple of 4 is passed
+ *     with a padded stride (for example the [:, :F] view of an [n, F + 3 & ~3]
+ *     buffer; the padding bytes are never read as features); a contiguous
+ *     one fails with NB_EINVAL before anything is enqueued.  nb_gather_features
+ *     and nb_quantize_fp8 take any stride.
  *   - Class labels: 0 = benign, 1 = malware for the two-class detector;
  *     exact ties are decided for the lowest class index (section 4: malware
  *     only if its posterior is higher, otherwise benign).

@@ -21,6 +21,13 @@ Tolerances, derived from the arithmetic of each GPU path:
   * labels: identical wherever the oracle's top-1 minus top-2 margin exceeds
     max(1e-3, the certified band): twice the largest centred-row bound, or
     the log-odds bound for two classes.
+  * beside the derived bound, every path with an FP32 table must also meet
+    the method's own score tolerance as read for FP32 arithmetic:
+    |ds_c| <= 1e-4 + 1e-6 (sum_f |g(x_f) W_cf| + |b_c|) on raw scores (the
+    1e-6 table tolerance carried through the sum), and that bound carried
+    through the log-sum-exp on log posteriors.  The derived bound is a
+    worst case, looser than this by up to the kernel's depth; this one is
+    what the method asks for.
 The literal 1e-4 absolute rate on raw scores is reported, not asserted: at
 |s| ~ 10^3 one FP32 ulp is already 6e-5.
 """
@@ -204,19 +211,34 @@ def assert_scores(om, X, labels, log_post, scores, wtype=W_F32, xtype=X_U8):
         band = 2.0 * post_err.max(axis=1)
         lp_tol = post_err + post_err.max(axis=1, keepdims=True) + 1e-5
         sc_tol = post_err + aux_err[:, None] + U * np.abs(s)
+    # The method's stated score tolerance, read for FP32 (|s| ~ 10^3 puts one
+    # ulp above 1e-4): |ds| <= 1e-4 + 1e-6 sum_f |g W_cf| (+ |b_c|), i.e. the
+    # table's 1e-6 relative tolerance carried through the sum.  A log
+    # posterior s_c - lse moves by at most |ds_c| + max_c' |ds_c'|.  Asserted
+    # on every path with an FP32 table, beside the kernel-derived bound.
+    c9 = 1e-4 + 1e-6 * (G @ np.abs(W).T + np.abs(b)[None, :])
+    c9_lp = c9 + c9.max(axis=1, keepdims=True)
     if scores is not None:
         err = np.abs(scores.astype(np.float64) - s)
         tol = sc_tol
         assert (err <= tol).all(), f"score error {err.max()} above bound (worst ratio {(err / tol).max():.3g})"
         stats["score_max_err"] = float(err.max())
         stats["score_literal_1e-4_rate"] = float((err <= 1e-4).mean())
-        c9 = 1e-4 + 1e-6 * (G @ np.abs(W).T + np.abs(b)[None, :])
-        stats["score_1e-6_relative_rate"] = float((err <= c9).mean())
+        stats["score_c9_rate"] = float((err <= c9).mean())
+        stats["score_c9_worst_ratio"] = float((err / c9).max())
+        if wtype == W_F32:
+            assert stats["score_c9_rate"] == 1.0, \
+                f"score error above 1e-4 + 1e-6 sum|gW| (worst ratio {stats['score_c9_worst_ratio']:.3g})"
     if log_post is not None:
         err = np.abs(log_post.astype(np.float64) - d.log_post)
         tol = lp_tol[:, None] if C == 2 else lp_tol
         assert (err <= tol).all(), f"log-posterior error {err.max()} above bound (worst ratio {(err / tol).max():.3g})"
+        stats["log_post_c9_rate"] = float((err <= c9_lp).mean())
+        if wtype == W_F32:
+            assert stats["log_post_c9_rate"] == 1.0, \
+                f"log-posterior error above the propagated 1e-4 + 1e-6 sum|gW| (worst ratio {(err / c9_lp).max():.3g})"
         perr = np.abs(np.exp(log_post.astype(np.float64)) - np.exp(d.log_post))
+        stats["post_1e-4_rate"] = float((perr.max(axis=1) <= 1e-4).mean())
         if wtype == W_F32:
             assert perr.max() <= 1e-4, f"posterior error {perr.max()}"
         else:   # reduced precision: the error is stated, bounded through the log posteriors:

@@ -99,6 +99,20 @@ def test_score_argument_errors(lib, kw, code):
     assert _score(lib, _model(), **kw) == code
 
 
+def test_odd_byte_width_needs_a_padded_stride(lib):
+    """A contiguous byte matrix with F = 513 has rows at every byte offset;
+    the rule (include/nb.h) is a stride that is a multiple of 4 bytes, so it
+    is refused before anything is enqueued (the padded case is a GPU test)."""
+    for C in (2, 7, 16):
+        m = _model(C=C, F=513)
+        for wt in (0, 1):
+            assert _score(lib, m, ld=513, wt=wt) == -1
+            assert b"multiple of 4" in lib.nb_last_error()
+        assert _train(lib, m, ld=513) == -1
+        assert b"multiple of 4" in lib.nb_last_error()
+    assert _score(lib, _model(F=513), ld=513, xtype=2) == -1      # FP8 bytes too
+
+
 def test_score_rejects_strides_beyond_the_staging_range(lib):
     """Every scoring path stages a group of rows through one buffer resource
     with 32-bit offsets: strides whose group spans 2 GiB are refused before

@@ -92,9 +92,10 @@ def test_fallback_routing_is_the_group_rule():
 
 
 @pytest.mark.parametrize("F,xdtype,fp8", [(100, torch.uint8, False), (1000, torch.uint8, False),
-                                          (64, torch.int32, False), (500, torch.uint8, True),
+                                          (64, torch.int32, False), (1000, torch.int32, False),
+                                          (1500, torch.int32, False), (500, torch.uint8, True),
                                           (5000, torch.uint8, False)],
-                         ids=["F100_u8", "F1000_u8", "F64_i32", "F500_fp8", "F5000_u8"])
+                         ids=["F100_u8", "F1000_u8", "F64_i32", "F1000_i32", "F1500_i32", "F500_fp8", "F5000_u8"])
 def test_groups_other_shapes(F, xdtype, fp8):
     _case(f"groups F={F} {xdtype} fp8={fp8}")
     models, oms, gmodel, xs, xo, route = _build(F, nb.MULTINOMIAL, xdtype=xdtype, fp8=fp8)

@@ -52,6 +52,35 @@ def test_fp32_vector_path(C, F, kind):
     assert_scores(om, to_np(Xt), to_np(lab), to_np(lp), to_np(sc) if with_scores else None)
 
 
+@pytest.mark.parametrize("C,wtype", [(7, 0), (2, 0), (16, 1)])
+def test_odd_feature_count_with_padded_stride(C, wtype):
+    """F = 513 byte features: the contiguous matrix is refused (stride not a
+    multiple of 4 bytes, include/nb.h), the same files behind a stride of
+    516 are trained and scored to parity."""
+    _case(f"F=513 padded C={C} wtype={wtype}")
+    F, ld = 513, 516
+    wl = family(C, F)
+    X, y = wl.train_set(6000, device=DEV)
+    m = nbg.Model(C, F, "multinomial")
+    with pytest.raises(nbg.NBError) as e:
+        nbg.train(m, X, y)
+    assert e.value.code == -1
+    pad = torch.zeros((X.shape[0], ld), dtype=torch.uint8, device=DEV)
+    pad[:, :F] = X
+    nbg.train(m, pad[:, :F], y)
+    om = nb.train(to_np(X), to_np(y), C, nb.MULTINOMIAL)
+    assert_tables(m, om, nb.MULTINOMIAL)
+    Xt, _ = wl.test_set(1001, device=DEV)
+    with pytest.raises(nbg.NBError) as e:
+        nbg.score(m, Xt, wtype=wtype)
+    assert e.value.code == -1
+    tp = torch.zeros((Xt.shape[0], ld), dtype=torch.uint8, device=DEV)
+    tp[:, :F] = Xt
+    lab, lp, sc = nbg.score(m, tp[:, :F], wtype=wtype, scores=True)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(Xt), to_np(lab), to_np(lp), to_np(sc), wtype=wtype)
+
+
 def test_int32_features_three_classes():
     wl = family(3, 64, p_zero=0.7, clip=False)
     m, om = _train(wl, 3000, nb.MULTINOMIAL)

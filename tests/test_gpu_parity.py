@@ -9,7 +9,7 @@ import torch
 import paper_1905_13746_amd as nbg
 from oracle import nb, precision as P
 from synth import workloads as W
-from tests.parity import assert_scores, assert_tables, to_np
+from tests.parity import X_I32, assert_scores, assert_tables, to_np
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -84,6 +84,63 @@ def test_int32_strided():
     lab, lp, sc = nbg.score(m, big[:, :64], scores=True)
     torch.cuda.synchronize()
     assert_scores(om, to_np(X), to_np(lab), to_np(lp), to_np(sc))
+
+
+# int32 features at widths where a file spans 64 lanes (F = 1000, 1001: the
+# last loads of a lane only partly live), several chunks (F = 1500, 5000),
+# contiguous and padded rows; test files carry counts well above 255 (every
+# other file scaled by 37) and a ragged last block.
+INT32_WIDE = [(1000, 1000, 3001), (1001, 1001, 2999), (1500, 1536, 1777), (5000, 5000, 1203)]
+
+
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+@pytest.mark.parametrize("F,ld,n", INT32_WIDE, ids=[f"F{f}_ld{ld}_n{n}" for f, ld, n in INT32_WIDE])
+def test_int32_two_class_wide(F, ld, n, kind):
+    _case(f"int32 two classes F={F} ld={ld} n={n} {kind}")
+    wl = W.Workload(wid=8, n_classes=2, n_features=F, p_zero=0.8, clip255=False, group=F)
+    m, om = _train_pair(wl, 6000 + 13, kind)
+    assert_tables(m, om, kind)
+    X, _ = wl.test_set(n, device=DEV)
+    X[::2] *= 37
+    buf = torch.zeros((n, ld), dtype=torch.int32, device=DEV)
+    buf[:, :F] = X
+    x = buf[:, :F]
+    lab, lp, sc = nbg.score(m, x, scores=True)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(X), to_np(lab), to_np(lp), to_np(sc), xtype=X_I32)
+    lab1, lp1, _ = nbg.score(m, x)
+    torch.cuda.synchronize()
+    assert_scores(om, to_np(X), to_np(lab1), to_np(lp1), None, xtype=X_I32)
+    # a view that ends exactly at the last feature of the last file
+    tight = buf.view(-1)[: (n - 1) * ld + F].as_strided((n, F), (ld, 1))
+    lab2, lp2, sc2 = nbg.score(m, tight, scores=True)
+    torch.cuda.synchronize()
+    assert torch.equal(lab2, lab) and torch.equal(lp2, lp) and torch.equal(sc2, sc)
+
+
+@pytest.mark.slow
+def test_full_size_int32_two_class_sampled():
+    """The int32-feature variant of the headline workload as the benchmark
+    runs it: 100,000 training files and 1,000,000 test files of F = 1000
+    int32 counts, one launch over every file; sampled files against the
+    oracle."""
+    _case("full size int32 F=1000")
+    wl = W.binary_u8(1000)
+    X, y = wl.train_set(100_000, device=DEV)
+    X = X.to(torch.int32)
+    m = nbg.Model(2, 1000, "multinomial")
+    nbg.train(m, X, y)
+    om = nb.train(to_np(X), to_np(y), 2, nb.MULTINOMIAL)
+    assert_tables(m, om, nb.MULTINOMIAL)
+    del X
+    Xt = wl.test_set(W.BINARY_TEST, device=DEV)[0].to(torch.int32)
+    lab, lp, _ = nbg.score(m, Xt)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([rng.choice(W.BINARY_TEST, 20_000, replace=False),
+                                    [0, 1, W.BINARY_TEST - 2, W.BINARY_TEST - 1]]))
+    it = torch.from_numpy(idx).to(DEV)
+    assert_scores(om, to_np(Xt[it]), to_np(lab[it]), to_np(lp[it]), None, xtype=X_I32)
 
 
 def test_train_on_strided_rows_matches():

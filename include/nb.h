@@ -316,6 +316,25 @@ int nb_score_groups(const nb_model* models, int32_t n_models, const nb_group* gr
                     int32_t xtype, int32_t wtype, int32_t tile_rows, void* workspace, size_t workspace_bytes,
                     void* stream);
 
+/* nb_score_groups for callers that cannot allocate device memory (code that
+ * must not call hipMalloc or a caching allocator, tight serving loops,
+ * harnesses that forbid allocation): no workspace argument; the work list
+ * goes to a fixed array inside the library, NB_SCORE_GROUPS_STATIC_MAX_BYTES
+ * bytes of device memory per device, held from the first call on that
+ * device until the process ends.  Arguments, schedules and outputs are those
+ * of nb_score_groups (the same kernels: bit-identical results).  A work list
+ * larger than the array (nb_score_groups_workspace_bytes() above the
+ * maximum) fails with NB_ENOMEM before anything is enqueued.  Allocates no
+ * device memory (the work list is built in host memory reused by later
+ * calls on the same thread).  Returns after `stream` has completed the
+ * launch.  Every call on a device shares that device's array, which keeps
+ * the last call's work list: calls that overlap on one device (from several
+ * host threads) race and must be serialised by the caller; calls made one
+ * after another never overlap.  Errors: those of nb_score_groups. */
+#define NB_SCORE_GROUPS_STATIC_MAX_BYTES (4u << 20)
+int nb_score_groups_static(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
+                           int32_t xtype, int32_t wtype, int32_t tile_rows, void* stream);
+
 /* A plan fixes one grouped call (models, groups, buffers, types) and holds
  * its work list in device memory plus a HIP graph of the launch: each
  * nb_group_plan_launch replays the graph (one kernel node, no memset; the

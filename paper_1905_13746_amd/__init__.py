@@ -311,13 +311,19 @@ class _GroupCall:
 
 
 def score_groups(models, groups, wtype: int = W_F32, fp8: bool = False, labels=True, log_post=True, scores=False,
-                 tile_rows: int = 0, outs=None, stream=None):
+                 tile_rows: int = 0, outs=None, stream=None, static: bool = False):
     """Score size groups in one launch.  groups: [(model index or None, x [n, F])]
     (None: no model of its own; the next group's model is used).  Returns the
-    per-group (labels, log_post, scores) outputs."""
+    per-group (labels, log_post, scores) outputs.  static=True calls
+    nb_score_groups_static (work list in the library's fixed device array, no
+    workspace allocated)."""
     lib = load()
     call = _GroupCall(models, groups, fp8, labels, log_post, scores, outs)
     cm, nm, cg, ng, xt = call.args()
+    if static:
+        check(lib.nb_score_groups_static(cm, nm, cg, ng, xt, int(wtype), int(tile_rows), _stream(stream)),
+              "nb_score_groups_static")
+        return call.outs
     ws_bytes = lib.nb_score_groups_workspace_bytes(cm, nm, cg, ng, xt, int(wtype), int(tile_rows))
     if ws_bytes == 0:   # invalid arguments: the call itself reports which
         check(lib.nb_score_groups(cm, nm, cg, ng, xt, int(wtype), int(tile_rows), None, 0, _stream(stream)),

@@ -101,6 +101,7 @@ SIGNATURES = {
     "nb_route_groups": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp]),
     "nb_score_groups_workspace_bytes": (_sz, [_PM, _i32, _PG, _i32, _i32, _i32, _i32]),
     "nb_score_groups": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _vp, _sz, _vp]),
+    "nb_score_groups_static": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _vp]),
     "nb_group_plan_create": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _i32, _vp,
                                             ctypes.POINTER(_vp)]),
     "nb_group_plan_launch": (ctypes.c_int, [_vp, _vp]),

@@ -86,11 +86,18 @@ class Workload:
     clip255: bool            # byte features (clip at 255) vs int32 (no clip)
     group: int = 0
     prior: np.ndarray | None = None   # None: balanced y_i = i mod C
+    near_tie: float = 0.0    # > 0: every class c > 0 gets lam[0, f] exp(near_tie z_cf)
     lam: np.ndarray = field(init=False)
 
     def __post_init__(self):
         rng = _np_rng(self.wid, ROLE_LAMBDA, self.group)
         self.lam = rng.gamma(0.5, 2.0, size=(self.n_classes, self.n_features))
+        if self.near_tie > 0.0:
+            # classes that differ only slightly: many files score close to a
+            # tie, which populates the label band of reduced-precision paths
+            z = _np_rng(self.wid, ROLE_LAMBDA, self.group, 1).standard_normal(
+                (self.n_classes - 1, self.n_features))
+            self.lam[1:] = self.lam[0][None, :] * np.exp(self.near_tie * z)
         self._tab = {}
 
     @property
@@ -165,6 +172,14 @@ def binary_u8(n_features: int = 1000) -> Workload:
 
 
 BINARY_TRAIN, BINARY_TEST = 200_000, 1_000_000
+
+
+def near_tie_u8(n_features: int = 1000, spread: float = 0.05) -> Workload:
+    """The byte two-class workload with near-tied classes: lam[1, f] =
+    lam[0, f] exp(spread z_f), z ~ N(0, 1) (not an experiment shape of the
+    paper: a stress case for the label decision)."""
+    return Workload(wid=7, n_classes=2, n_features=n_features, p_zero=0.8, clip255=True,
+                    near_tie=spread)
 
 
 def family16() -> Workload:

@@ -37,7 +37,8 @@ def test_generator_gpu_equals_cpu():
 
 
 CASES = [("tiny_int32", W.tiny_int32, W.TINY_TRAIN, W.TINY_TEST)] + [
-    (f"binary_u8_F{F}", (lambda F=F: W.binary_u8(F)), 20_000 + 37, 6_000 + 5) for F in (100, 500, 1000, 5000)]
+    (f"binary_u8_F{F}", (lambda F=F: W.binary_u8(F)), 20_000 + 37, 6_000 + 5) for F in (100, 500, 1000, 5000)] + [
+    ("near_tie_u8_F1000", W.near_tie_u8, 20_000 + 37, 30_000 + 5)]
 
 
 @pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
@@ -197,11 +198,12 @@ def test_quantize_kernel_bit_exact():
 
 
 @pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
-def test_bf16_table_within_certified_band(kind):
-    _case(f"bf16 {kind}")
-    wl = W.binary_u8(1000)
+@pytest.mark.parametrize("near_tie", [False, True], ids=["binary_u8", "near_tie_u8"])
+def test_bf16_table_within_certified_band(kind, near_tie):
+    _case(f"bf16 {kind} near_tie={near_tie}")
+    wl = W.near_tie_u8(1000) if near_tie else W.binary_u8(1000)
     m, om = _train_pair(wl, 20_000, kind)
-    X, _ = wl.test_set(5000, device=DEV)
+    X, _ = wl.test_set(30_000 if near_tie else 5000, device=DEV)
     lab, lp, sc = nbg.score(m, X, wtype=nbg.W_BF16, scores=True)
     torch.cuda.synchronize()
     Xn = to_np(X)
@@ -214,6 +216,8 @@ def test_bf16_table_within_certified_band(kind):
     d = nb.decide(s)
     gate = d.margin > np.maximum(1e-3, band)
     assert (to_np(lab)[gate] == d.labels[gate]).all()
+    if near_tie:   # the case exists to put files inside the band
+        assert (~gate).sum() > 0
     # arithmetic parity against the rounded table itself
     g = (Xn > 0).astype(np.float64) if kind == nb.BERNOULLI else Xn.astype(np.float64)
     exact_h = P.posterior_rows(rh, bh, Xn, kind == nb.BERNOULLI)[:, 0]

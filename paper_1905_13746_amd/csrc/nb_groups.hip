@@ -55,13 +55,16 @@ struct GroupsArgs {
   const GroupItem* items;    // dynamic: [n_items], largest first; stream: fast items in memory order
   const GroupItem* tails;    // stream: [n_tails] blocks needing guarded loads
   const int64_t* gstart;     // static: [n_groups + 1] first block of each group
+  const int64_t* sstart;     // sweep: [n_groups + 1] first sweep block of each group
   int32_t* counter;          // dynamic: [2] next item, finished workgroups
   int32_t n_items;
   int32_t n_tails;
   int32_t n_groups;
   int32_t Fp;                // padded feature count (every group's model has the same F)
   int32_t nch;               // feature chunks per row
-  int64_t total_blocks;
+  int32_t F;                 // features (sweep)
+  int32_t wt;                // table type (sweep)
+  int64_t total_blocks;      // every block (static), or the sweep's blocks (sweep)
 };
 
 // ---- stream schedule (tables of at most kStreamTable floats: NS * Fp)
@@ -274,15 +277,252 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
   }
 }
 
-template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+// The stream schedule with flat staging (two-chunk byte rows; see
+// score_blocks): a sweep, the single-model kernel's order over the
+// concatenation of every group's blocks.  Wave w of the grid takes sweep
+// blocks w, w + W, w + 2W, ... (W waves), so the machine reads one window of
+// memory at a time and every wave gets the same number of blocks.  Each
+// block is fetched as ONE aligned window of FL 1 KB pieces into the wave's
+// LDS region and read back row by row with the lane mapping of the direct
+// loads (identical arithmetic).  The groups' prefix block counts and a
+// compact copy of their descriptors (with the row biases) sit in LDS, so
+// finding the next block's group (a ballot over the prefix counts) and its
+// window never waits on memory: it runs while the current block's window
+// is in flight, and the next block's loads (window and each lane's table
+// weights) go out as soon as the current window has landed.  No barrier in
+// the sweep.  Groups smaller than a window are tails, scored afterwards
+// with the table in LDS.
+constexpr int kSweepMaxGroups = 320;
+constexpr int kSweepRun = 4;
+
+struct SweepDesc {                 // one group as the sweep reads it (LDS)
+  const uint8_t* x;
+  int64_t ld_bytes;
+  int64_t total_bytes;
+  int64_t n;
+  const void* table;               // rows32 or rows16 (the call's table type)
+  int32_t* labels;
+  float* log_post;
+  float* scores;
+  float rb[2];
+};
+static_assert(sizeof(SweepDesc) == 72, "sweep descriptor layout");
+
+template <int XT, int NS, bool BIN, bool MULTI, int FL, bool BF>
+__global__ __launch_bounds__(kThreads) void score2_groups_sweep_kernel(GroupsArgs g) {
+  constexpr int LPR = 64;
+  constexpr int R = block_steps<XT, false, MULTI, FL>();
+  constexpr int BR = R;                 // one row per row-step
+  constexpr int CW = 16 * LPR;
+  constexpr int NCH = 2;                // two chunks per row
+  constexpr int kPiece = 64 * 16;
+  static_assert(XT != NB_X_I32 && MULTI, "the sweep stages two-chunk byte rows");
+  __shared__ __attribute__((aligned(16))) uint8_t flat_all[kWaves * flat_region_bytes(FL)];
+  __shared__ float stage[kWaves][NS][BR];
+  __shared__ int64_t s_start[kSweepMaxGroups + 1];
+  __shared__ SweepDesc s_desc[kSweepMaxGroups];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = lane;
+  const int ng = g.n_groups;
+  constexpr bool bf = BF;               // BF16 table (else FP32)
+  constexpr int TW = BF ? 2 : 4;        // 16-byte table loads per lane, chunk and row
+  const int F = g.F, Fp = g.Fp;
+  for (int t = threadIdx.x; t <= ng; t += kThreads) s_start[t] = g.sstart[t];
+  for (int t = threadIdx.x; t < ng; t += kThreads) {
+    const Score2Args& a = g.descs[t];
+    SweepDesc d;
+    d.x = a.x;
+    d.ld_bytes = a.ld_bytes;
+    d.total_bytes = a.total_bytes;
+    d.n = a.n;
+    d.table = bf ? (const void*)a.rows16 : (const void*)a.rows32;
+    d.labels = a.labels;
+    d.log_post = a.log_post;
+    d.scores = a.scores;
+    d.rb[0] = a.n > 0 ? a.row_bias[0] : 0.0f;
+    d.rb[1] = a.n > 0 ? a.row_bias[NS - 1] : 0.0f;
+    s_desc[t] = d;
+  }
+  __syncthreads();
+
+  // Order: rounds of kSweepRun consecutive blocks per wave (wave w takes
+  // blocks w*RUN .. w*RUN + RUN-1 of each round of W*RUN), so a wave's next
+  // block is usually in the same group and keeps its table registers; the
+  // blocks after the last whole round go one per wave.
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t total = g.total_blocks;
+  const int64_t round = nwaves * kSweepRun;
+  const int64_t full = total / round;                 // whole rounds
+  const int64_t rem = total - full * round;
+  const int nb = (int)(full * kSweepRun + (rem > gw ? (rem - gw - 1) / nwaves + 1 : 0));
+  auto sweep_block = [&](int k) -> int64_t {
+    const int64_t kf = full * kSweepRun;
+    if (k < kf) return (k / kSweepRun) * round + gw * kSweepRun + (k % kSweepRun);
+    return full * round + gw + (int64_t)(k - kf) * nwaves;
+  };
+  uint8_t* mine = flat_all + wave * flat_region_bytes(FL);
+
+  float acc[R][NS];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+  uint32_t keep[4] = {~0u, ~0u, ~0u, ~0u};
+
+  if (nb > 0) {
+    // ---- a block ready to launch: its group, place and outputs
+    struct Next {
+      const uint8_t* base;              // first byte of its window
+      const void* table;
+      int32_t* labels;
+      float* log_post;
+      float* scores;
+      float rb[2];
+      int64_t lb;                       // block index inside its group
+      int32_t ld;
+      uint32_t lead;
+      int32_t nrows;
+      int32_t group;
+    };
+    int gi = 0;                         // group of the block last prepared
+    auto prep = [&](int k, Next& nx) {
+      const int64_t sb = sweep_block(k);
+      // the last group whose first sweep block is <= sb: the entries past
+      // gi that are <= sb form a prefix (the counts never decrease)
+      for (;;) {
+        const int e = gi + 1 + lane;
+        const bool le = e <= ng && s_start[e <= ng ? e : ng] <= sb;
+        const int adv = __popcll(__ballot(le));
+        gi += adv;
+        if (adv < 64) break;
+      }
+      const SweepDesc& d = s_desc[gi];
+      const uint8_t* x = dev::uniform_ptr(d.x);
+      const int64_t ldb = d.ld_bytes;
+      nx.group = gi;
+      nx.lb = sb - s_start[gi];
+      const int64_t s0 = nx.lb * BR * ldb;
+      const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(x + s0) & 127u);
+      const int64_t w0 = s0 >= mis ? s0 - mis : 0;
+      const int64_t last = d.total_bytes - (int64_t)FL * 1024;
+      const int64_t ws = w0 < last ? w0 : last;
+      nx.base = x + ws;
+      nx.lead = (uint32_t)(s0 - ws);
+      const int64_t left = d.n - nx.lb * BR;
+      nx.nrows = left < BR ? (int)left : BR;
+      nx.ld = (int32_t)ldb;
+      nx.table = d.table;
+      nx.labels = d.labels;
+      nx.log_post = d.log_post;
+      nx.scores = d.scores;
+      nx.rb[0] = d.rb[0];
+      nx.rb[1] = d.rb[1];
+    };
+    dev::u32x4 fb[FL];
+    auto launch = [&](const Next& nx) {
+      const uint32_t span = nx.lead + (uint32_t)((nx.nrows - 1) * nx.ld + F);
+      // the window lies in bounds (the host stages only buffers holding a window)
+      const auto rsrc = dev::make_rsrc(dev::uniform_ptr(nx.base), (int64_t)FL * 1024);
+#pragma unroll
+      for (int q = 0; q < FL; ++q) {
+        const uint32_t off = (uint32_t)(q * kPiece + 16 * lane);
+        fb[q] = dev::buffer_load16(rsrc, off < span ? off : dev::kNoAccess);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    // each lane's 16 weights of each chunk and row, as raw words (FP32: four
+    // 16-byte loads; BF16: two)
+    dev::u32x4 wt[NCH][NS][TW];
+    auto load_table_regs = [&](const void* table) {
+      const auto trs = dev::make_rsrc(dev::uniform_ptr(table), NS * Fp * (bf ? 2 : 4));
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+          for (int q = 0; q < TW; ++q)
+            wt[c][s2][q] = dev::buffer_load16(trs, (uint32_t)(s2 * Fp + c * CW + 16 * j) * (bf ? 2u : 4u) + 16u * q);
+    };
+
+    Next cur, nxt;
+    prep(0, cur);
+    launch(cur);
+    load_table_regs(cur.table);
+    if (nb > 1) prep(1, nxt);
+    for (int k = 0; k < nb; ++k) {
+      // the launched block lands in LDS; the next one goes out
+#pragma unroll
+      for (int q = 0; q < FL; ++q) *reinterpret_cast<dev::u32x4*>(mine + q * kPiece + 16 * lane) = fb[q];
+      const bool more = k + 1 < nb;
+      if (more) launch(nxt);
+
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        float w[NS][16];
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            if constexpr (BF) {
+              const uint32_t word16 = wt[c][s2][e >> 3][(e >> 1) & 3];
+              w[s2][e] = __uint_as_float((e & 1) ? (word16 & 0xFFFF0000u) : (word16 << 16));
+            } else {
+              w[s2][e] = __uint_as_float(wt[c][s2][(e >> 2) % TW][e & 3]);
+            }
+          }
+        const int fc = c * CW + 16 * j;
+        if (XT == NB_X_FP8) fp8_keep_mask(F, fc, keep);
+        read_flat_rows<XT, NS, BIN, R>(mine + cur.lead + (uint32_t)fc, (uint32_t)cur.ld, fc < F, w, keep, acc);
+      }
+      Score2Args a{};
+      a.labels = cur.labels;
+      a.log_post = cur.log_post;
+      a.scores = cur.scores;
+      float rb[NS];
+      rb[0] = cur.rb[0];
+      rb[NS - 1] = cur.rb[NS - 1];
+      // a group's last block may be partial: its rows past the end hold
+      // stale bytes and are never stored
+      if (cur.nrows == BR) finish_block<LPR, NS, true>(a, acc, lane, wave, 0, rb, cur.lb * BR, BR, stage);
+      else finish_block<LPR, NS, false>(a, acc, lane, wave, 0, rb, cur.lb * BR, cur.nrows, stage);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) acc[i][s2] = 0.0f;
+      // the next block's table, when its group differs (the loads land
+      // with its window)
+      if (more && nxt.group != cur.group) load_table_regs(nxt.table);
+      cur = nxt;
+      if (k + 2 < nb) prep(k + 2, nxt);
+    }
+  }
+
+  // ---- groups smaller than a window: the table in LDS (the staging regions
+  // are free once every wave of the workgroup has left the sweep)
+  float* tbl = reinterpret_cast<float*>(flat_all);
+  for (int t = blockIdx.x; t < g.n_tails; t += (int)gridDim.x) {
+    const GroupItem it = dev::load_uniform(g.tails + t);
+    const Score2Args a = dev::load_uniform(g.descs + it.group);
+    __syncthreads();
+    stage_table<NS>(a, tbl);
+    __syncthreads();
+    score_blocks<XT, LPR, NS, BIN, MULTI>(a, tbl, it.block0 + wave, kWaves, it.block0 + it.nblocks, stage);
+  }
+}
+
+template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
 __global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsArgs g) {
-  extern __shared__ float tbl[];        // [NS][Fp] of the current group
-  __shared__ float stage[kWaves][NS][(64 / LPR) * row_steps<XT, false>()];
+  extern __shared__ float tbl[];        // [NS][Fp] of the current group, then the flat staging regions
+  __shared__ float stage[kWaves][NS][(64 / LPR) * block_steps<XT, false, MULTI, FL>()];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t B = g.total_blocks;
   int64_t b = B * blockIdx.x / gridDim.x;
   const int64_t b1 = B * (blockIdx.x + 1) / gridDim.x;
   if (b >= b1) return;
+  uint8_t* flat = FL ? reinterpret_cast<uint8_t*>(tbl) + (size_t)NS * g.Fp * sizeof(float) : nullptr;
   // the group holding block b: the last gi with gstart[gi] <= b
   int lo = 0, hi = g.n_groups - 1;
   while (lo < hi) {
@@ -298,17 +538,18 @@ __global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsAr
     __syncthreads();                            // the previous group's table is no longer read
     stage_table<NS>(a, tbl);
     __syncthreads();
-    score_blocks<XT, LPR, NS, BIN, MULTI>(a, tbl, (b - gs) + wave, kWaves, seg_end - gs, stage);
+    score_blocks<XT, LPR, NS, BIN, MULTI, false, FL>(a, tbl, (b - gs) + wave, kWaves, seg_end - gs, stage, flat);
     b = seg_end;
   }
 }
 
-template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
 __global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g) {
-  extern __shared__ float tbl[];        // [NS][Fp] of the current item's group
-  __shared__ float stage[kWaves][NS][(64 / LPR) * row_steps<XT, false>()];
+  extern __shared__ float tbl[];        // [NS][Fp] of the current item's group, then the flat staging regions
+  __shared__ float stage[kWaves][NS][(64 / LPR) * block_steps<XT, false, MULTI, FL>()];
   __shared__ int32_t s_item;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint8_t* flat = FL ? reinterpret_cast<uint8_t*>(tbl) + (size_t)NS * g.Fp * sizeof(float) : nullptr;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(g.counter, 1);
     // the barrier also ends every read of the previous item's table
@@ -319,7 +560,8 @@ __global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g) {
     const Score2Args a = dev::load_uniform(g.descs + item.group);
     stage_table<NS>(a, tbl);
     __syncthreads();
-    score_blocks<XT, LPR, NS, BIN, MULTI>(a, tbl, item.block0 + wave, kWaves, item.block0 + item.nblocks, stage);
+    score_blocks<XT, LPR, NS, BIN, MULTI, false, FL>(a, tbl, item.block0 + wave, kWaves, item.block0 + item.nblocks,
+                                                     stage, flat);
   }
   // every workgroup has taken its last item when the finished count reaches
   // the grid size: the last one re-arms the counters for the next launch
@@ -333,24 +575,39 @@ __global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g) {
   }
 }
 
+// The dynamic and static schedules take direct loads only: with flat
+// staging's one workgroup per CU, their per-item barriers and table
+// stages stall the CU (measured slower than direct loads).
 struct Grouped {
-  template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+  template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
   static const void* fn() {
-    return reinterpret_cast<const void*>(score2_groups_kernel<XT, LPR, NS, BIN, MULTI>);
+    if constexpr (FL != 0) return nullptr;
+    else return reinterpret_cast<const void*>(score2_groups_kernel<XT, LPR, NS, BIN, MULTI>);
   }
 };
 
 struct GroupedStream {
-  template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+  template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
   static const void* fn() {
-    return reinterpret_cast<const void*>(score2_groups_stream_kernel<XT, LPR, NS, BIN, MULTI>);
+    if constexpr (FL != 0) return nullptr;   // the stream schedule stages no rows
+    else return reinterpret_cast<const void*>(score2_groups_stream_kernel<XT, LPR, NS, BIN, MULTI>);
+  }
+};
+
+template <bool BF>
+struct GroupedSweep {
+  template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
+  static const void* fn() {
+    if constexpr (FL == 0 || LPR != 64 || XT == NB_X_I32 || !MULTI) return nullptr;
+    else return reinterpret_cast<const void*>(score2_groups_sweep_kernel<XT, NS, BIN, MULTI, FL, BF>);
   }
 };
 
 struct GroupedStatic {
-  template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+  template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
   static const void* fn() {
-    return reinterpret_cast<const void*>(score2_groups_static_kernel<XT, LPR, NS, BIN, MULTI>);
+    if constexpr (FL != 0) return nullptr;
+    else return reinterpret_cast<const void*>(score2_groups_static_kernel<XT, LPR, NS, BIN, MULTI>);
   }
 };
 
@@ -364,7 +621,9 @@ struct GroupSetup {
   int F = 0, lpr = 0, ns = 1, nch = 1;
   bool bin = false;
   int xtype = 0, wtype = 0;
-  size_t lds = 0;
+  size_t lds = 0;                  // table bytes in LDS
+  int fl = 0;                      // flat staging pieces of the sweep (stream schedule), 0: none
+  size_t lds_dyn = 0;              // dynamic LDS of the static and dynamic kernels
   const void* fn = nullptr;        // dynamic-item kernel
   const void* fn_static = nullptr; // static-range kernel
   const void* fn_stream = nullptr; // stream kernel (tables of at most kStreamTable floats)
@@ -402,7 +661,15 @@ int setup_groups(const nb_model* models, int32_t n_models, const nb_group* group
   S->descs.resize(n_groups);
   S->blocks.assign(n_groups, 0);
   S->lpr = lanes_per_row(S->F);
-  const int64_t br = (int64_t)(64 / S->lpr) * row_steps_of(xtype, false);
+  // flat staging when every non-empty group qualifies (the largest window)
+  S->fl = -1;
+  for (int32_t g = 0; g < n_groups && S->fl != 0; ++g) {
+    if (groups[g].n <= 0) continue;
+    const int f = flat_pieces(xtype, S->F, groups[g].ld * (int64_t)elem_bytes(xtype), groups[g].x, false);
+    S->fl = (f == 0) ? 0 : std::max(S->fl, f);
+  }
+  if (S->fl < 0) S->fl = 0;
+  const int64_t br = (int64_t)(64 / S->lpr) * block_steps_of(xtype, false, (S->F + 16 * S->lpr - 1) / (16 * S->lpr), S->fl);
   for (int32_t g = 0; g < n_groups; ++g) {
     const nb_group& G = groups[g];
     const nb_model* m = &models[groups[route[g]].model];
@@ -418,7 +685,8 @@ int setup_groups(const nb_model* models, int32_t n_models, const nb_group* group
       nb_layout L;
       int rc = check_score_args(m, &L, G.x, xtype, G.n, G.ld, wtype, G.labels, G.log_post, G.scores);
       if (rc) return fail(rc, "group " + std::to_string(g) + ": " + nb_last_error());
-      rc = make_score2_args(m, L, G.x, xtype, G.n, G.ld, wtype, G.labels, G.log_post, G.scores, S->ns, &a);
+      rc = make_score2_args(m, L, G.x, xtype, G.n, G.ld, wtype, G.labels, G.log_post, G.scores, S->ns, &a, false,
+                            S->fl);
       if (rc) return rc;
       S->blocks[g] = (G.n + br - 1) / br;
       S->n_files += G.n;
@@ -440,18 +708,27 @@ int setup_groups(const nb_model* models, int32_t n_models, const nb_group* group
   S->nch = (S->F + cw - 1) / cw;
   S->fn = pick_score2<Grouped>(xtype, S->lpr, S->nch > 1, S->ns, S->bin);
   S->fn_static = pick_score2<GroupedStatic>(xtype, S->lpr, S->nch > 1, S->ns, S->bin);
-  if (S->lds > 64 * 1024) {
-    NB_HIP_CHECK(hipFuncSetAttribute(S->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds));
-    NB_HIP_CHECK(hipFuncSetAttribute(S->fn_static, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds));
+  S->lds_dyn = S->lds;
+  if (S->lds_dyn > 64 * 1024) {
+    NB_HIP_CHECK(hipFuncSetAttribute(S->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_dyn));
+    NB_HIP_CHECK(hipFuncSetAttribute(S->fn_static, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_dyn));
   }
   S->Fp = L.padded_features;
   S->stream_ok = (size_t)S->ns * L.padded_features <= (size_t)kStreamTable;
-  if (S->stream_ok) {
+  // with flat staging the stream schedule is a sweep: its tables ride in
+  // registers (tails stage one group's rows in LDS), any NS
+  if (S->fl > 0 && n_groups > kSweepMaxGroups) S->fl = 0;   // the sweep keeps every group's descriptor in LDS
+  if (S->fl > 0) {
+    S->stream_ok = true;
+    S->fn_stream = wtype == NB_W_BF16 ? pick_score2<GroupedSweep<true>>(xtype, S->lpr, S->nch > 1, S->ns, S->bin, S->fl)
+                                      : pick_score2<GroupedSweep<false>>(xtype, S->lpr, S->nch > 1, S->ns, S->bin, S->fl);
+    S->grid_cap_stream = resident_per_cu(S->fn_stream, kThreads, 0) * device_cu_count();
+  } else if (S->stream_ok) {
     S->fn_stream = pick_score2<GroupedStream>(xtype, S->lpr, S->nch > 1, S->ns, S->bin);
     S->grid_cap_stream = resident_per_cu(S->fn_stream, kThreads, 0) * device_cu_count();
   }
-  S->grid_cap = resident_per_cu(S->fn, kThreads, S->lds) * device_cu_count();
-  S->grid_cap_static = resident_per_cu(S->fn_static, kThreads, S->lds) * device_cu_count();
+  S->grid_cap = resident_per_cu(S->fn, kThreads, S->lds_dyn) * device_cu_count();
+  S->grid_cap_static = resident_per_cu(S->fn_static, kThreads, S->lds_dyn) * device_cu_count();
   for (int64_t b : S->blocks) S->total_blocks += b;
   return NB_OK;
 }
@@ -467,7 +744,7 @@ int default_tile_blocks(const GroupSetup& S) {
 }
 
 int tile_blocks_from_rows(const GroupSetup& S, int32_t tile_rows) {
-  const int br = (64 / S.lpr) * row_steps_of(S.xtype, false);
+  const int br = (64 / S.lpr) * block_steps_of(S.xtype, false, S.nch, S.fl);
   const int64_t b = ((int64_t)tile_rows + br - 1) / br;
   return (int)std::max<int64_t>(kWaves, (b + kWaves - 1) / kWaves * kWaves);
 }
@@ -492,9 +769,11 @@ std::vector<GroupItem> make_items(const GroupSetup& S, int tile_blocks) {
 //    (n_groups + 1 int64); dynamic: items; stream: items, then tails]
 struct WorkList {
   int code = 0;
+  bool sweep = false;              // stream code with flat staging: sstart + tails
   std::vector<GroupItem> items;
   std::vector<GroupItem> tails;
   std::vector<int64_t> gstart;
+  std::vector<int64_t> sstart;     // sweep: first sweep block of each group, then the total
   bool is_static() const { return code == 0; }
   bool is_stream() const { return code < 0; }
   int32_t n_items() const { return (int32_t)items.size(); }
@@ -523,10 +802,28 @@ void make_stream_items(const GroupSetup& S, int T, WorkList* w) {
   }
 }
 
+// Sweep: each group's staged blocks (below its nflat) in memory order, as
+// prefix counts over the groups; the blocks past them are tails.
+void make_sweep_list(const GroupSetup& S, WorkList* w) {
+  w->sweep = true;
+  w->sstart.resize(S.blocks.size() + 1);
+  int64_t acc = 0;
+  for (size_t g = 0; g < S.blocks.size(); ++g) {
+    w->sstart[g] = acc;
+    const int64_t nb = S.blocks[g];
+    const int64_t ns = std::min<int64_t>(nb, S.descs[g].nflat);
+    acc += ns;
+    if (ns < nb) w->tails.push_back(GroupItem{ns, (int32_t)g, (int32_t)(nb - ns)});
+  }
+  w->sstart[S.blocks.size()] = acc;
+}
+
 WorkList make_work_list(const GroupSetup& S, int code) {
   WorkList w;
   w.code = code;
-  if (code == 0) {
+  if (code < 0 && S.fl > 0) {
+    make_sweep_list(S, &w);
+  } else if (code == 0) {
     w.gstart.resize(S.blocks.size() + 1);
     int64_t acc = 0;
     for (size_t g = 0; g < S.blocks.size(); ++g) {
@@ -544,6 +841,7 @@ WorkList make_work_list(const GroupSetup& S, int code) {
 
 size_t payload_bytes(const WorkList& w) {
   if (w.is_static()) return w.gstart.size() * sizeof(int64_t);
+  if (w.sweep) return align_up(w.sstart.size() * sizeof(int64_t), 16) + w.tails.size() * sizeof(GroupItem);
   return (w.items.size() + w.tails.size()) * sizeof(GroupItem);
 }
 
@@ -574,6 +872,10 @@ void serialise(const GroupSetup& S, const WorkList& w, std::vector<uint8_t>* blo
   uint8_t* pay = blob->data() + kCounterBytes + align_up(ng * sizeof(Score2Args), kAlign);
   if (w.is_static()) {
     std::memcpy(pay, w.gstart.data(), w.gstart.size() * sizeof(int64_t));
+  } else if (w.sweep) {
+    std::memcpy(pay, w.sstart.data(), w.sstart.size() * sizeof(int64_t));
+    std::memcpy(pay + align_up(w.sstart.size() * sizeof(int64_t), 16), w.tails.data(),
+                w.tails.size() * sizeof(GroupItem));
   } else {
     std::memcpy(pay, w.items.data(), w.items.size() * sizeof(GroupItem));
     std::memcpy(pay + w.items.size() * sizeof(GroupItem), w.tails.data(), w.tails.size() * sizeof(GroupItem));
@@ -585,9 +887,10 @@ struct LaunchDesc {
   const void* fn = nullptr;
   size_t lds = 0;
   int grid = 0;
-  int kind = 0;                // 0 static, 1 dynamic, 2 stream
-  int32_t n_items = 0, n_tails = 0, n_groups = 0, Fp = 0, nch = 0;
+  int kind = 0;                // 0 static, 1 dynamic, 2 stream, 3 sweep
+  int32_t n_items = 0, n_tails = 0, n_groups = 0, Fp = 0, nch = 0, F = 0, wt = 0;
   int64_t total_blocks = 0;
+  int64_t sweep_blocks = 0;
 };
 
 LaunchDesc describe(const GroupSetup& S, const WorkList& w) {
@@ -597,19 +900,28 @@ LaunchDesc describe(const GroupSetup& S, const WorkList& w) {
   L.n_groups = (int32_t)S.descs.size();
   L.Fp = S.Fp;
   L.nch = S.nch;
+  L.F = S.F;
+  L.wt = S.wtype;
   L.total_blocks = S.total_blocks;
   if (w.is_static()) {
     L.kind = 0;
     L.fn = S.fn_static;
-    L.lds = S.lds;
+    L.lds = S.lds_dyn;
     // every workgroup gets at least a few blocks per wave
     const int64_t most = std::max<int64_t>(1, S.total_blocks / (2 * kWaves));
     L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(S.grid_cap_static, most));
   } else if (w.code > 0) {
     L.kind = 1;
     L.fn = S.fn;
-    L.lds = S.lds;
+    L.lds = S.lds_dyn;
     L.grid = std::max(1, std::min(S.grid_cap, L.n_items));
+  } else if (w.sweep) {
+    L.kind = 3;
+    L.fn = S.fn_stream;
+    L.lds = 0;
+    L.sweep_blocks = w.sstart.back();
+    const int64_t most = std::max<int64_t>({1, (L.sweep_blocks + kWaves - 1) / kWaves, (int64_t)L.n_tails});
+    L.grid = (int)std::min<int64_t>(S.grid_cap_stream, most);
   } else {
     L.kind = 2;
     L.fn = S.fn_stream;
@@ -627,9 +939,17 @@ int launch_grouped(const LaunchDesc& L, const DevLists& d, hipStream_t s) {
   g.n_groups = L.n_groups;
   g.Fp = L.Fp;
   g.nch = L.nch;
+  g.F = L.F;
+  g.wt = L.wt;
   g.total_blocks = L.total_blocks;
   if (L.kind == 0) {
     g.gstart = static_cast<const int64_t*>(d.payload);
+  } else if (L.kind == 3) {
+    g.sstart = static_cast<const int64_t*>(d.payload);
+    g.tails = reinterpret_cast<const GroupItem*>(static_cast<const uint8_t*>(d.payload) +
+                                                 align_up(((size_t)L.n_groups + 1) * sizeof(int64_t), 16));
+    g.n_tails = L.n_tails;
+    g.total_blocks = L.sweep_blocks;
   } else {
     g.items = static_cast<const GroupItem*>(d.payload);
     g.n_items = L.n_items;
@@ -739,7 +1059,10 @@ int prepare_group_launch(const nb_model* models, int32_t n_models, const nb_grou
   out->n_groups = L.n_groups;
   out->Fp = L.Fp;
   out->nch = L.nch;
+  out->F = L.F;
+  out->wt = L.wt;
   out->total_blocks = L.total_blocks;
+  out->sweep_blocks = L.sweep_blocks;
   out->blob_bytes = blob->size();
   return NB_OK;
 }
@@ -755,7 +1078,10 @@ int enqueue_group_launch(const GroupLaunch& G, void* dev_blob, hipStream_t s) {
   L.n_groups = G.n_groups;
   L.Fp = G.Fp;
   L.nch = G.nch;
+  L.F = G.F;
+  L.wt = G.wt;
   L.total_blocks = G.total_blocks;
+  L.sweep_blocks = G.sweep_blocks;
   return launch_grouped(L, carve(dev_blob, G.n_groups), s);
 }
 
@@ -957,13 +1283,14 @@ int nb_group_plan_launch(nb_group_plan* plan, void* stream) {
 
 int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out) {
   if (!plan || !out) return fail(NB_EINVAL, "NULL argument");
-  const int br = (64 / plan->S.lpr) * row_steps_of(plan->S.xtype, false);
+  const int br = (64 / plan->S.lpr) * block_steps_of(plan->S.xtype, false, plan->S.nch, plan->S.fl);
   const LaunchDesc L = describe(plan->S, plan->w);
   const int code = plan->w.code;
   out->schedule = code == 0 ? NB_SCHEDULE_STATIC : (code > 0 ? NB_SCHEDULE_DYNAMIC : NB_SCHEDULE_STREAM);
   out->tile_rows = code == 0 ? (int32_t)std::min<int64_t>(INT32_MAX, (plan->S.total_blocks + L.grid - 1) / L.grid * br)
-                             : std::abs(code) * br;
-  out->n_items = code == 0 ? L.grid : L.n_items + L.n_tails;
+                             : (plan->w.sweep ? br : std::abs(code) * br);
+  out->n_items = code == 0 ? L.grid
+                           : (int32_t)std::min<int64_t>(INT32_MAX, (plan->w.sweep ? L.sweep_blocks : L.n_items) + L.n_tails);
   out->grid = L.grid;
   out->tuned = plan->tuned;
   out->n_files = plan->S.n_files;

@@ -80,13 +80,16 @@ struct GroupLaunch {
   const void* fn = nullptr;
   size_t lds = 0;
   int32_t grid = 0;
-  int32_t kind = 0;            // schedule: 0 static ranges, 1 dynamic items, 2 stream
+  int32_t kind = 0;            // schedule: 0 static ranges, 1 dynamic items, 2 stream, 3 sweep
   int32_t n_items = 0;
   int32_t n_tails = 0;
   int32_t n_groups = 0;
   int32_t Fp = 0;
   int32_t nch = 0;
+  int32_t F = 0;
+  int32_t wt = 0;
   int64_t total_blocks = 0;
+  int64_t sweep_blocks = 0;    // sweep: blocks of the sweep (the rest are tails)
   size_t blob_bytes = 0;
 };
 int prepare_group_launch(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,

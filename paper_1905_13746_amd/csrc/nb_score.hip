@@ -32,25 +32,28 @@
 namespace nb {
 namespace {
 
-template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false>
+template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false, int FL = 0>
 __global__ __launch_bounds__(kThreads) void score2_kernel(Score2Args a) {
-  extern __shared__ float tbl[];        // [NS][Fp] (Gaussian: [4][Fp], means then h)
-  __shared__ float stage[kWaves][NS][(64 / LPR) * row_steps<XT, QUAD>()];
+  // [NS][Fp] (Gaussian: [4][Fp], means then h); with flat staging, then the
+  // waves' staging regions (kWaves x FL KB)
+  extern __shared__ float tbl[];
+  __shared__ float stage[kWaves][NS][(64 / LPR) * block_steps<XT, QUAD, MULTI, FL>()];
   if constexpr (QUAD) stage_table_q(a, tbl);
   else stage_table<NS>(a, tbl);
   __syncthreads();
-  constexpr int BR = (64 / LPR) * row_steps<XT, QUAD>();
+  constexpr int BR = (64 / LPR) * block_steps<XT, QUAD, MULTI, FL>();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wave_id = (int64_t)blockIdx.x * kWaves + wave;
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
   const int64_t nblk = (a.n + BR - 1) / BR;
-  score_blocks<XT, LPR, NS, BIN, MULTI, QUAD>(a, tbl, wave_id, nwaves, nblk, stage);
+  uint8_t* flat = FL ? reinterpret_cast<uint8_t*>(tbl) + (size_t)NS * a.Fp * sizeof(float) : nullptr;
+  score_blocks<XT, LPR, NS, BIN, MULTI, QUAD, FL>(a, tbl, wave_id, nwaves, nblk, stage, flat);
 }
 
 struct Single {
-  template <int XT, int LPR, int NS, bool BIN, bool MULTI>
+  template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
   static const void* fn() {
-    return reinterpret_cast<const void*>(score2_kernel<XT, LPR, NS, BIN, MULTI>);
+    return reinterpret_cast<const void*>(score2_kernel<XT, LPR, NS, BIN, MULTI, false, FL>);
   }
 };
 
@@ -78,14 +81,15 @@ int launch_score2(const nb_model* m, const nb_layout& L, const void* x, int32_t 
   const int ns = scores ? 2 : 1;
   const bool quad = (m->kind == NB_GAUSSIAN);
   Score2Args a;
-  const int rc = make_score2_args(m, L, x, xtype, n, ld, wtype, labels, log_post, scores, ns, &a, quad);
+  const int fl = quad ? 0 : flat_pieces(xtype, m->n_features, ld * elem_bytes(xtype), x, false);
+  const int rc = make_score2_args(m, L, x, xtype, n, ld, wtype, labels, log_post, scores, ns, &a, quad, fl);
   if (rc) return rc;
   const int lpr = lanes_per_row(a.F);
-  const size_t lds = (size_t)(quad ? 4 : ns) * a.Fp * sizeof(float);
+  const size_t lds = (size_t)(quad ? 4 : ns) * a.Fp * sizeof(float) + (fl ? (size_t)kWaves * flat_region_bytes(fl) : 0);
   const void* fn = quad ? pick_quad(xtype, lpr, a.nch > 1, ns)
-                        : pick_score2<Single>(xtype, lpr, a.nch > 1, ns, m->kind == NB_BERNOULLI);
+                        : pick_score2<Single>(xtype, lpr, a.nch > 1, ns, m->kind == NB_BERNOULLI, fl);
   if (lds > 64 * 1024) NB_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int64_t rows_per_blk = (int64_t)(64 / lpr) * row_steps_of(xtype, quad);
+  const int64_t rows_per_blk = (int64_t)(64 / lpr) * block_steps_of(xtype, quad, a.nch, fl);
   const int64_t nblk = (n + rows_per_blk - 1) / rows_per_blk;
   const int64_t want = (nblk + kWaves - 1) / kWaves;
   const int64_t cap = (int64_t)resident_per_cu(fn, kThreads, lds) * device_cu_count();

@@ -9,6 +9,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "nb_device.hpp"
 #include "nb_internal.hpp"
@@ -41,6 +42,11 @@ constexpr int row_steps() { return (QUAD || XT == NB_X_I32) ? NB_ROW_STEPS_HEAVY
 inline int row_steps_of(int xtype, bool quad) {
   return (quad || xtype == NB_X_I32) ? NB_ROW_STEPS_HEAVY : NB_ROW_STEPS;
 }
+// Row-steps per block of a two-class kernel (one name for the block size of
+// every variant, direct loads or flat staging).
+template <int XT, bool QUAD, bool MULTI, int FL>
+constexpr int block_steps() { return row_steps<XT, QUAD>(); }
+inline int block_steps_of(int xtype, bool quad, int nch, int fl) { return row_steps_of(xtype, quad); }
 // the transposed butterfly of finish_block halves R x NS values per step
 static_assert((NB_ROW_STEPS & (NB_ROW_STEPS - 1)) == 0 && (NB_ROW_STEPS_HEAVY & (NB_ROW_STEPS_HEAVY - 1)) == 0,
               "row steps per block must be powers of two");
@@ -60,6 +66,7 @@ struct Score2Args {
   float* log_post;
   float* scores;
   int64_t nfast;            // leading blocks with every row present and in bounds
+  int64_t nflat;            // leading blocks scored through flat staging (all or none)
   int32_t F, Fp, nch, wt;
 };
 
@@ -322,6 +329,63 @@ __device__ __forceinline__ void stage_table_q(const Score2Args& a, float* tbl) {
     tbl[2 * a.Fp + i] = (a.wt == NB_W_BF16) ? dev::bf16_to_f32(a.rows16_q[i]) : a.rows32_q[i];
 }
 
+// ---- flat staging helpers (see score_blocks)
+// LDS bytes of one wave's staging region: the window, then 16 bytes that
+// catch the reads of a row's last 16-byte piece past the window's end.
+__host__ __device__ constexpr int flat_region_bytes(int fl) { return fl * 1024 + 16; }
+
+// Start of a block's window, relative to a.x: the cache line holding the
+// block's first byte (x itself when that line begins before the buffer),
+// moved back so that the window ends inside the buffer (the host stages a
+// block only when the buffer holds at least a window).
+__device__ __forceinline__ int64_t flat_window_start(const Score2Args& a, int64_t s0, int fl) {
+  const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(a.x + s0) & 127u);
+  const int64_t w0 = s0 >= mis ? s0 - mis : 0;
+  const int64_t last = a.total_bytes - (int64_t)fl * 1024;
+  return w0 < last ? w0 : last;
+}
+
+// Rows of block blk (all BR but for a buffer's partial last block).
+template <int BR>
+__device__ __forceinline__ int flat_block_rows(const Score2Args& a, int64_t blk) {
+  const int64_t left = a.n - blk * BR;
+  return left < BR ? (int)left : BR;
+}
+
+// Accumulate the R rows of one chunk from a staged window: lane j reads its
+// 16 bytes of each row (rows 8-byte aligned in LDS, the host's condition:
+// two 8-byte reads); a lane whose features all lie past F reads nothing
+// (its weights are zero: the same sums).
+// Rows are read four at a time (the scheduler would otherwise hoist every
+// row's LDS read ahead of the arithmetic: 64 registers).
+template <int XT, int NS, bool BIN, int R>
+__device__ __forceinline__ void read_flat_rows(const uint8_t* p, uint32_t ld, bool live, const float (&w)[NS][16],
+                                               const uint32_t (&keep)[4], float (&acc)[R][NS]) {
+  constexpr int kBatch = R < 4 ? R : 4;
+#pragma unroll
+  for (int i0 = 0; i0 < R; i0 += kBatch) {
+    dev::u32x4 v[kBatch][1];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      v[b][0] = dev::u32x4{0u, 0u, 0u, 0u};
+      if (live) {
+        const uint2* q2 = reinterpret_cast<const uint2*>(p + (uint32_t)(i0 + b) * ld);
+        const uint2 lo = q2[0], hi = q2[1];
+        v[b][0] = dev::u32x4{lo.x, lo.y, hi.x, hi.y};
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (XT == NB_X_FP8) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[b][0][d] &= keep[d];
+      }
+      accumulate_seg<XT, NS, BIN>(v[b], w, acc[i0 + b]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // One wave scores the blocks first, first + stride, ... below `end` of the
 // files described by `a` (a block is R row-steps of 64/LPR rows; rows are
 // relative to a.x and to the output pointers).  Blocks below a.nfast take
@@ -330,13 +394,20 @@ __device__ __forceinline__ void stage_table_q(const Score2Args& a, float* tbl) {
 // accumulated.  The rest take guarded loads.  tbl: the rows in LDS.
 // MULTI: F spans more than one chunk of 16*LPR features (only with LPR = 64).
 // QUAD: a Gaussian model (x and x^2 rows, see accumulate_seg_q).
-template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false>
+// FL > 0: byte features with one row per row-step: the blocks below a.nflat
+// are fetched as ONE aligned byte range (FL pieces of 1 KB per wave: whole
+// cache lines per load instruction, however the rows fall on lines) into the
+// wave's region of `flat` (LDS, kWaves * FL KB), and each row is then read
+// from LDS with the same lane mapping, so the arithmetic is unchanged.
+template <int XT, int LPR, int NS, bool BIN, bool MULTI, bool QUAD = false, int FL = 0>
 __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* tbl, int64_t first, int64_t stride,
-                                             int64_t end, float (*stage)[NS][(64 / LPR) * row_steps<XT, QUAD>()]) {
+                                             int64_t end,
+                                             float (*stage)[NS][(64 / LPR) * block_steps<XT, QUAD, MULTI, FL>()],
+                                             uint8_t* flat = nullptr) {
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
   constexpr int NV = EB;
   constexpr int G = 64 / LPR;           // rows per row-step
-  constexpr int R = row_steps<XT, QUAD>();
+  constexpr int R = block_steps<XT, QUAD, MULTI, FL>();
   constexpr int BR = G * R;             // rows per block
   constexpr int CW = 16 * LPR;          // features per chunk
   using LM = LaneMap<XT, LPR>;
@@ -378,9 +449,66 @@ __device__ __forceinline__ void score_blocks(const Score2Args& a, const float* t
     else accumulate_rows<XT, NS, BIN, NV>(v, w, keep, true, acc);
   };
 
+  // ---- flat blocks: first + k*stride < min(end, nflat)
+  if constexpr (FL > 0) {
+    static_assert(XT != NB_X_I32 && LPR == 64 && !QUAD, "flat staging: byte features, one row per row-step");
+    constexpr int kPiece = 64 * 16;     // bytes of one wave load instruction
+    uint8_t* mine = flat + (size_t)wave * flat_region_bytes(FL);
+    const int64_t flat_end = a.nflat < end ? a.nflat : end;
+    const int nb = (flat_end > first) ? (int)((flat_end - first + stride - 1) / stride) : 0;
+    dev::u32x4 fb[FL];
+    uint32_t lead_next = 0;
+    auto issue_flat = [&](int k) {
+      const int64_t blk = first + (int64_t)k * stride;
+      const int64_t s0 = blk * BR * ld;
+      const int64_t w0 = flat_window_start(a, s0, FL);
+      lead_next = (uint32_t)(s0 - w0);
+      const uint32_t span = lead_next + (uint32_t)((flat_block_rows<BR>(a, blk) - 1) * ld + a.F);
+      const auto rsrc = dev::make_rsrc(dev::uniform_ptr(a.x + w0), dev::uniform64(a.total_bytes - w0));
+#pragma unroll
+      for (int q = 0; q < FL; ++q) {
+        const uint32_t off = (uint32_t)(q * kPiece + 16 * lane);
+        fb[q] = dev::buffer_load16(rsrc, off < span ? off : dev::kNoAccess);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    auto consume_flat = [&](uint32_t lead, int64_t blk) {
+      for (int ch = 0; ch < nch; ++ch) {
+        const int fc = ch * CW + 16 * j;
+        if (MULTI) {
+          load_w(fc);
+          if (XT == NB_X_FP8) fp8_keep_mask(a.F, fc, keep);
+        }
+        read_flat_rows<XT, NS, BIN, R>(mine + lead + (uint32_t)fc, (uint32_t)ld, fc < a.F, w, keep, acc);
+      }
+      // a buffer's last block may be partial (its window moved back from
+      // the end): rows past it hold stale bytes and are never stored
+      const int nrows = flat_block_rows<BR>(a, blk);
+      if (nrows == BR) finish_block<LPR, NS, true>(a, acc, lane, wave, sub, rb, blk * BR, BR, stage);
+      else finish_block<LPR, NS, false>(a, acc, lane, wave, sub, rb, blk * BR, nrows, stage);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[i][s] = 0.0f;
+    };
+    if (nb > 0) {
+      issue_flat(0);
+      for (int k = 0; k < nb; ++k) {
+#pragma unroll
+        for (int q = 0; q < FL; ++q) *reinterpret_cast<dev::u32x4*>(mine + q * kPiece + 16 * lane) = fb[q];
+        const uint32_t lead = lead_next;
+        if (k + 1 < nb) issue_flat(k + 1);
+        consume_flat(lead, first + (int64_t)k * stride);
+      }
+    }
+    first += (int64_t)nb * stride;
+  }
+
   // ---- fast blocks: first + i*stride < min(end, nfast).  Per-wave counters
-  // are 32-bit so loop control stays on the scalar unit.
-  const int64_t fast_end = a.nfast < end ? a.nfast : end;
+  // are 32-bit so loop control stays on the scalar unit.  (Flat kernels
+  // leave the few blocks past nflat to the guarded loop: the double buffer
+  // of their block size would not fit the register file.)
+  const int64_t fast_end = FL > 0 ? first : (a.nfast < end ? a.nfast : end);
   const int my_blocks = (fast_end > first) ? (int)((fast_end - first + stride - 1) / stride) : 0;
   const int units = my_blocks * nch;
   dev::u32x4 buf0[R][NV], buf1[R][NV];
@@ -514,11 +642,37 @@ int lanes_per_row(int F) {
 
 constexpr size_t kMaxTableLds = 128 * 1024;
 
+// Flat staging (score_blocks with FL > 0): 1 KB pieces per wave (32), or 0
+// when the call does not qualify.  It needs byte features in two chunks per
+// row (1024 < F), rows 8-byte aligned (x, the stride and F), little padding
+// between rows (the window fetches it), and a block's window (up to 127
+// bytes before its first row, its rows, each lane's last chunk) within
+// 32 KB.  NB_FLAT_ROWS=0 in the environment turns it off.
+constexpr int64_t kFlatMinBlock = 28 * 1024;
+inline int flat_pieces(int xtype, int F, int64_t ld_bytes, const void* x, bool quad) {
+  static const bool off = [] {
+    const char* e = std::getenv("NB_FLAT_ROWS");
+    return e && e[0] == '0';
+  }();
+  if (off || quad || xtype == NB_X_I32 || lanes_per_row(F) != 64) return 0;
+  // 8-byte aligned rows and buffer end: windows (including those moved
+  // back from the end) keep every row 8-byte aligned in LDS
+  if (((reinterpret_cast<uintptr_t>(x) | (uintptr_t)ld_bytes | (uintptr_t)F) & 7u) != 0) return 0;
+  if (ld_bytes * 16 > (int64_t)F * 17) return 0;
+  const int nch = (F + 1023) / 1024;
+  const int64_t rows = block_steps_of(xtype, false, nch, 32);
+  const int64_t need = 127 + (rows - 1) * ld_bytes + (int64_t)nch * 1024;
+  // two-chunk rows only, a window within 32 KB that carries enough bytes to
+  // keep the wave's loads in flight (measured on gfx950: one-chunk rows and
+  // smaller blocks run no faster, or slower, than direct loads)
+  return (nch == 2 && need <= 32 * 1024 && rows * ld_bytes >= kFlatMinBlock) ? 32 : 0;
+}
+
 // Launch arguments of the two-class kernels for one model and one feature
 // matrix (arguments already validated).  Returns NB_OK or NB_EINVAL.
 int make_score2_args(const nb_model* m, const nb_layout& L, const void* x, int32_t xtype, int64_t n, int64_t ld,
                      int32_t wtype, int32_t* labels, float* log_post, float* scores, int ns, Score2Args* out,
-                     bool quad = false) {
+                     bool quad = false, int fl = 0) {
   const int F = m->n_features;
   const int eb = elem_bytes(xtype);
   const int lpr = lanes_per_row(F);
@@ -545,7 +699,7 @@ int make_score2_args(const nb_model* m, const nb_layout& L, const void* x, int32
   a.Fp = L.padded_features;
   a.nch = nch;
   a.wt = wtype;
-  const int64_t rows_per_blk = (int64_t)(64 / lpr) * row_steps_of(xtype, quad);
+  const int64_t rows_per_blk = (int64_t)(64 / lpr) * block_steps_of(xtype, quad, nch, fl);
   if (rows_per_blk * a.ld_bytes >= (int64_t)1 << 31)
     return fail(NB_EINVAL, "row stride too large (a block of rows must span < 2 GiB)");
   // leading blocks whose rows all exist and whose loads stay inside the buffer
@@ -553,34 +707,43 @@ int make_score2_args(const nb_model* m, const nb_layout& L, const void* x, int32
   const int64_t full = n / rows_per_blk;
   const int64_t rmax = (a.total_bytes >= span) ? (a.total_bytes - span) / a.ld_bytes : -1;
   a.nfast = std::max<int64_t>(0, std::min(full, (rmax + 1) / rows_per_blk));
+  // flat staging: every block, the partial last one included, once the
+  // buffer holds a whole window (windows near the end are moved back
+  // inside the buffer)
+  a.nflat = (fl > 0 && a.total_bytes >= (int64_t)fl * 1024) ? (n + rows_per_blk - 1) / rows_per_blk : 0;
   *out = a;
   return NB_OK;
 }
 
-// Kernel pointer of a two-class kernel family: Fam::fn<XT, LPR, NS, BIN, MULTI>().
+// Kernel pointer of a two-class kernel family: Fam::fn<XT, LPR, NS, BIN,
+// MULTI, FL>() (FL: flat staging pieces, byte features with LPR = 64 only).
 template <class Fam, int XT, int NS, bool BIN>
-const void* pick_lpr(int lpr, bool multi) {
+const void* pick_lpr(int lpr, bool multi, int fl) {
   switch (lpr) {
     case 4: return Fam::template fn<XT, 4, NS, BIN, false>();
     case 8: return Fam::template fn<XT, 8, NS, BIN, false>();
     case 16: return Fam::template fn<XT, 16, NS, BIN, false>();
     case 32: return Fam::template fn<XT, 32, NS, BIN, false>();
-    default: return multi ? Fam::template fn<XT, 64, NS, BIN, true>() : Fam::template fn<XT, 64, NS, BIN, false>();
+    default:
+      if constexpr (XT != NB_X_I32) {
+        if (fl == 32 && multi) return Fam::template fn<XT, 64, NS, BIN, true, 32>();
+      }
+      return multi ? Fam::template fn<XT, 64, NS, BIN, true>() : Fam::template fn<XT, 64, NS, BIN, false>();
   }
 }
 
 template <class Fam, int XT>
-const void* pick_ns_bin(int lpr, bool multi, int ns, bool bin) {
-  if (ns == 1) return bin ? pick_lpr<Fam, XT, 1, true>(lpr, multi) : pick_lpr<Fam, XT, 1, false>(lpr, multi);
-  return bin ? pick_lpr<Fam, XT, 2, true>(lpr, multi) : pick_lpr<Fam, XT, 2, false>(lpr, multi);
+const void* pick_ns_bin(int lpr, bool multi, int ns, bool bin, int fl) {
+  if (ns == 1) return bin ? pick_lpr<Fam, XT, 1, true>(lpr, multi, fl) : pick_lpr<Fam, XT, 1, false>(lpr, multi, fl);
+  return bin ? pick_lpr<Fam, XT, 2, true>(lpr, multi, fl) : pick_lpr<Fam, XT, 2, false>(lpr, multi, fl);
 }
 
 template <class Fam>
-const void* pick_score2(int xtype, int lpr, bool multi, int ns, bool bin) {
+const void* pick_score2(int xtype, int lpr, bool multi, int ns, bool bin, int fl = 0) {
   switch (xtype) {
-    case NB_X_U8: return pick_ns_bin<Fam, NB_X_U8>(lpr, multi, ns, bin);
-    case NB_X_I32: return pick_ns_bin<Fam, NB_X_I32>(lpr, multi, ns, bin);
-    default: return pick_ns_bin<Fam, NB_X_FP8>(lpr, multi, ns, bin);
+    case NB_X_U8: return pick_ns_bin<Fam, NB_X_U8>(lpr, multi, ns, bin, fl);
+    case NB_X_I32: return pick_ns_bin<Fam, NB_X_I32>(lpr, multi, ns, bin, 0);
+    default: return pick_ns_bin<Fam, NB_X_FP8>(lpr, multi, ns, bin, fl);
   }
 }
 

@@ -281,10 +281,14 @@ int nb_route_groups(const int64_t* class_counts_host, int32_t n_groups, int32_t 
  * Schedules: stream (the default when NS x Fp <= 2048 table floats: groups
  * cut into items of a few blocks, taken round-robin in memory order, each
  * wave's loads pipelined across items, the next item's table loaded with
- * them), static ranges (each workgroup scores an equal contiguous run of
- * files, staging a group's table in LDS when its run enters that group), or
- * dynamic items (groups cut into tiles of tile_rows files, taken largest
- * first from a device counter).
+ * them; for byte features of 1025 to 2036 features per file with 8-byte
+ * aligned rows and at most 320 groups, a sweep instead: every wave takes
+ * runs of four blocks of the concatenated groups in memory order, each
+ * block fetched as one window of whole cache lines into LDS), static ranges
+ * (each workgroup scores an equal contiguous run of files, staging a
+ * group's table in LDS when its run enters that group), or dynamic items
+ * (groups cut into tiles of tile_rows files, taken largest first from a
+ * device counter).
  *
  * One group of files (device pointers as for nb_score): */
 typedef struct {
@@ -310,8 +314,11 @@ typedef struct {
 size_t nb_score_groups_workspace_bytes(const nb_model* models, int32_t n_models, const nb_group* groups,
                                        int32_t n_groups, int32_t xtype, int32_t wtype, int32_t tile_rows);
 /* Build the work list, copy it into `workspace` (256-byte aligned, caller
- * owned) and launch.  Returns after `stream` has completed the launch (the
- * work list is staged from host memory); use a plan for repeated scoring. */
+ * owned) and launch: the list is staged through pinned host memory of the
+ * library (allocated on first use, reused once its copy has run), so the
+ * call returns once the copy and the launch are enqueued on `stream`.  The
+ * workspace and the outputs must stay valid until the stream has passed
+ * the launch; use a plan for repeated scoring. */
 int nb_score_groups(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
                     int32_t xtype, int32_t wtype, int32_t tile_rows, void* workspace, size_t workspace_bytes,
                     void* stream);
@@ -373,6 +380,25 @@ typedef struct {
 int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
                          int32_t xtype, int32_t wtype, int32_t tile_rows, int32_t flags, void* stream,
                          nb_group_plan** out);
+/* A new step for an existing plan (sections 3-4: each step's files fall into
+ * size groups of varying sizes): the same models' kind and feature count,
+ * the same requested outputs, at most the plan's number of groups, any group
+ * sizes, inputs and outputs.  The new work list (same schedule) is written
+ * into the plan through pinned host memory and one copy enqueued on
+ * `stream`; the captured graph is not touched (its kernel reads the counts
+ * from the work list), so the next nb_group_plan_launch on `stream` scores
+ * the new groups.  Returns without waiting for the device, except that a
+ * third update waits until the first one's copy has run (two staging
+ * buffers).  Launch and update a plan on one stream.  Room: work lists up
+ * to four times the payload of the largest list the creation call could
+ * make, and at least 1 MiB (65,536 items of the dynamic and stream
+ * schedules; the sweep's and static ranges' lists do not grow with the
+ * files).  Errors: NB_EINVAL (arguments, more groups than at creation, or
+ * groups needing another kernel: another feature count or kind, other
+ * outputs, rows that no longer qualify for the plan's row staging),
+ * NB_ENOMEM (work list beyond the plan's room), NB_EHIP. */
+int nb_group_plan_update(nb_group_plan* plan, const nb_model* models, int32_t n_models, const nb_group* groups,
+                         int32_t n_groups, void* stream);
 int nb_group_plan_launch(nb_group_plan* plan, void* stream);
 int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out);
 /* Waits for the device, then frees the plan (NULL is a no-op). */

@@ -360,6 +360,19 @@ class GroupPlan:
     def outs(self):
         return self.call.outs
 
+    def update(self, models, groups, fp8: bool = False, labels=True, log_post=True, scores=False, outs=None,
+               stream=None):
+        """A new step: re-point the plan at these groups (same models' kind
+        and feature count, same outputs, at most the creation's number of
+        groups); the next launch() on the same stream scores them.  Returns
+        the new per-group outputs."""
+        call = _GroupCall(models, groups, fp8, labels, log_post, scores, outs)
+        cm, nm, cg, ng, _ = call.args()
+        check(self._lib.nb_group_plan_update(self.handle, cm, nm, cg, ng, _stream(stream)), "nb_group_plan_update")
+        # the plan's copies of the old step may still be in flight: keep both
+        self._prev, self.call = self.call, call
+        return call.outs
+
     def launch(self, stream=None):
         check(self._lib.nb_group_plan_launch(self.handle, _stream(stream)), "nb_group_plan_launch")
 

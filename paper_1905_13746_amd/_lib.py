@@ -104,6 +104,7 @@ SIGNATURES = {
     "nb_score_groups_static": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _vp]),
     "nb_group_plan_create": (ctypes.c_int, [_PM, _i32, _PG, _i32, _i32, _i32, _i32, _i32, _vp,
                                             ctypes.POINTER(_vp)]),
+    "nb_group_plan_update": (ctypes.c_int, [_vp, _PM, _i32, _PG, _i32, _vp]),
     "nb_group_plan_launch": (ctypes.c_int, [_vp, _vp]),
     "nb_group_plan_query": (ctypes.c_int, [_vp, ctypes.POINTER(NbGroupPlanInfo)]),
     "nb_group_plan_destroy": (ctypes.c_int, [_vp]),

@@ -32,6 +32,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <sstream>
 #include <string>
@@ -50,22 +51,52 @@ struct GroupItem {
 static_assert(sizeof(GroupItem) == 16, "item layout");
 static_assert(sizeof(Score2Args) <= kGroupDescBound, "descriptor bound used by serving");
 
-struct GroupsArgs {
-  const Score2Args* descs;   // [n_groups]
-  const GroupItem* items;    // dynamic: [n_items], largest first; stream: fast items in memory order
-  const GroupItem* tails;    // stream: [n_tails] blocks needing guarded loads
-  const int64_t* gstart;     // static: [n_groups + 1] first block of each group
-  const int64_t* sstart;     // sweep: [n_groups + 1] first sweep block of each group
-  int32_t* counter;          // dynamic: [2] next item, finished workgroups
+// Counts of a work list, in its device header right after the two dynamic
+// counters: kernels read them at launch, so a captured launch picks up a
+// work list rewritten in place (nb_group_plan_update).
+struct ListCounts {
   int32_t n_items;
   int32_t n_tails;
   int32_t n_groups;
+  int32_t kind;              // 0 static, 1 dynamic, 2 stream, 3 sweep
+  int64_t total_blocks;      // every block (static), or the sweep's blocks (sweep)
+};
+static_assert(sizeof(ListCounts) == 24, "work-list header layout");
+
+struct GroupsArgs {
+  const Score2Args* descs;   // [n_groups]
+  const void* payload;       // the work list's payload (see make_work_list)
+  const ListCounts* counts;  // in the work list's header
+  int32_t* counter;          // dynamic: [2] next item, finished workgroups
   int32_t Fp;                // padded feature count (every group's model has the same F)
   int32_t nch;               // feature chunks per row
   int32_t F;                 // features (sweep)
   int32_t wt;                // table type (sweep)
+  // resolved from the header by each kernel (resolve_list)
+  const GroupItem* items;    // dynamic: [n_items], largest first; stream: fast items in memory order
+  const GroupItem* tails;    // stream, sweep: [n_tails] blocks scored after the items
+  const int64_t* gstart;     // static: [n_groups + 1] first block of each group
+  const int64_t* sstart;     // sweep: [n_groups + 1] first sweep block of each group
+  int32_t n_items;
+  int32_t n_tails;
+  int32_t n_groups;
   int64_t total_blocks;      // every block (static), or the sweep's blocks (sweep)
 };
+
+__device__ __forceinline__ GroupsArgs resolve_list(GroupsArgs g) {
+  const ListCounts c = dev::load_uniform(g.counts);
+  const uint8_t* pay = static_cast<const uint8_t*>(g.payload);
+  g.n_items = c.n_items;
+  g.n_tails = c.n_tails;
+  g.n_groups = c.n_groups;
+  g.total_blocks = c.total_blocks;
+  g.items = reinterpret_cast<const GroupItem*>(pay);
+  g.gstart = reinterpret_cast<const int64_t*>(pay);
+  g.sstart = reinterpret_cast<const int64_t*>(pay);
+  g.tails = (c.kind == 3) ? reinterpret_cast<const GroupItem*>(pay + (((size_t)c.n_groups + 1) * 8 + 15) / 16 * 16)
+                          : g.items + c.n_items;
+  return g;
+}
 
 // ---- stream schedule (tables of at most kStreamTable floats: NS * Fp)
 // Workgroup w takes the fast items w, w + grid, ... in memory order, so the
@@ -96,7 +127,8 @@ __device__ __forceinline__ void lds_only_barrier() {
 }
 
 template <int XT, int LPR, int NS, bool BIN, bool MULTI>
-__global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsArgs g) {
+__global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsArgs g_in) {
+  const GroupsArgs g = resolve_list(g_in);
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;
   constexpr int NV = EB;
   constexpr int G = 64 / LPR;
@@ -309,7 +341,8 @@ struct SweepDesc {                 // one group as the sweep reads it (LDS)
 static_assert(sizeof(SweepDesc) == 72, "sweep descriptor layout");
 
 template <int XT, int NS, bool BIN, bool MULTI, int FL, bool BF>
-__global__ __launch_bounds__(kThreads) void score2_groups_sweep_kernel(GroupsArgs g) {
+__global__ __launch_bounds__(kThreads) void score2_groups_sweep_kernel(GroupsArgs g_in) {
+  const GroupsArgs g = resolve_list(g_in);
   constexpr int LPR = 64;
   constexpr int R = block_steps<XT, false, MULTI, FL>();
   constexpr int BR = R;                 // one row per row-step
@@ -514,7 +547,8 @@ __global__ __launch_bounds__(kThreads) void score2_groups_sweep_kernel(GroupsArg
 }
 
 template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
-__global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsArgs g) {
+__global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsArgs g_in) {
+  const GroupsArgs g = resolve_list(g_in);
   extern __shared__ float tbl[];        // [NS][Fp] of the current group, then the flat staging regions
   __shared__ float stage[kWaves][NS][(64 / LPR) * block_steps<XT, false, MULTI, FL>()];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -544,7 +578,8 @@ __global__ __launch_bounds__(kThreads) void score2_groups_static_kernel(GroupsAr
 }
 
 template <int XT, int LPR, int NS, bool BIN, bool MULTI, int FL = 0>
-__global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g) {
+__global__ __launch_bounds__(kThreads) void score2_groups_kernel(GroupsArgs g_in) {
+  const GroupsArgs g = resolve_list(g_in);
   extern __shared__ float tbl[];        // [NS][Fp] of the current item's group, then the flat staging regions
   __shared__ float stage[kWaves][NS][(64 / LPR) * block_steps<XT, false, MULTI, FL>()];
   __shared__ int32_t s_item;
@@ -845,31 +880,48 @@ size_t payload_bytes(const WorkList& w) {
   return (w.items.size() + w.tails.size()) * sizeof(GroupItem);
 }
 
-size_t work_list_bytes(size_t n_groups, size_t payload) {
-  return kCounterBytes + align_up(n_groups * sizeof(Score2Args), kAlign) + align_up(payload, kAlign);
+// A work list's device image:
+//   [header, kCounterBytes: two int32 counters (zero), then ListCounts]
+//   [descriptors: room for cap_groups, 256-byte aligned]
+//   [payload]
+// cap_groups is the call's group count, or a plan's capacity.
+size_t work_list_bytes(size_t cap_groups, size_t payload) {
+  return kCounterBytes + align_up(cap_groups * sizeof(Score2Args), kAlign) + align_up(payload, kAlign);
 }
 
 struct DevLists {
   int32_t* counter;
+  const ListCounts* counts;
   Score2Args* descs;
   void* payload;
 };
 
-DevLists carve(void* ws, size_t n_groups) {
+DevLists carve(void* ws, size_t cap_groups) {
   uint8_t* p = static_cast<uint8_t*>(ws);
   DevLists d;
   d.counter = reinterpret_cast<int32_t*>(p);
+  d.counts = reinterpret_cast<const ListCounts*>(p + 2 * sizeof(int32_t));
   d.descs = reinterpret_cast<Score2Args*>(p + kCounterBytes);
-  d.payload = p + kCounterBytes + align_up(n_groups * sizeof(Score2Args), kAlign);
+  d.payload = p + kCounterBytes + align_up(cap_groups * sizeof(Score2Args), kAlign);
   return d;
 }
 
+int list_kind(const WorkList& w) { return w.is_static() ? 0 : (w.code > 0 ? 1 : (w.sweep ? 3 : 2)); }
+
 // The device image of a work list (counters zeroed).
-void serialise(const GroupSetup& S, const WorkList& w, std::vector<uint8_t>* blob) {
+void serialise(const GroupSetup& S, const WorkList& w, std::vector<uint8_t>* blob, size_t cap_groups = 0) {
   const size_t ng = S.descs.size();
-  blob->assign(work_list_bytes(ng, payload_bytes(w)), 0);
+  if (cap_groups < ng) cap_groups = ng;
+  blob->assign(work_list_bytes(cap_groups, payload_bytes(w)), 0);
+  ListCounts c{};
+  c.n_items = w.n_items();
+  c.n_tails = w.n_tails();
+  c.n_groups = (int32_t)ng;
+  c.kind = list_kind(w);
+  c.total_blocks = w.sweep ? w.sstart.back() : S.total_blocks;
+  std::memcpy(blob->data() + 2 * sizeof(int32_t), &c, sizeof c);
   std::memcpy(blob->data() + kCounterBytes, S.descs.data(), ng * sizeof(Score2Args));
-  uint8_t* pay = blob->data() + kCounterBytes + align_up(ng * sizeof(Score2Args), kAlign);
+  uint8_t* pay = blob->data() + kCounterBytes + align_up(cap_groups * sizeof(Score2Args), kAlign);
   if (w.is_static()) {
     std::memcpy(pay, w.gstart.data(), w.gstart.size() * sizeof(int64_t));
   } else if (w.sweep) {
@@ -882,7 +934,8 @@ void serialise(const GroupSetup& S, const WorkList& w, std::vector<uint8_t>* blo
   }
 }
 
-// Launch of one work list: kernel, grid and the arguments it needs.
+// Launch of one work list: kernel, grid and the arguments it needs (the
+// counts travel in the list's header).
 struct LaunchDesc {
   const void* fn = nullptr;
   size_t lds = 0;
@@ -893,7 +946,9 @@ struct LaunchDesc {
   int64_t sweep_blocks = 0;
 };
 
-LaunchDesc describe(const GroupSetup& S, const WorkList& w) {
+// fixed_grid: the resident grid of the schedule's kernel whatever the list
+// (a plan's captured launch serves every work list written into it)
+LaunchDesc describe(const GroupSetup& S, const WorkList& w, bool fixed_grid = false) {
   LaunchDesc L;
   L.n_items = w.n_items();
   L.n_tails = w.n_tails();
@@ -903,59 +958,41 @@ LaunchDesc describe(const GroupSetup& S, const WorkList& w) {
   L.F = S.F;
   L.wt = S.wtype;
   L.total_blocks = S.total_blocks;
-  if (w.is_static()) {
-    L.kind = 0;
+  L.kind = list_kind(w);
+  if (L.kind == 0) {
     L.fn = S.fn_static;
     L.lds = S.lds_dyn;
     // every workgroup gets at least a few blocks per wave
     const int64_t most = std::max<int64_t>(1, S.total_blocks / (2 * kWaves));
-    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(S.grid_cap_static, most));
-  } else if (w.code > 0) {
-    L.kind = 1;
+    L.grid = fixed_grid ? S.grid_cap_static : (int)std::max<int64_t>(1, std::min<int64_t>(S.grid_cap_static, most));
+  } else if (L.kind == 1) {
     L.fn = S.fn;
     L.lds = S.lds_dyn;
-    L.grid = std::max(1, std::min(S.grid_cap, L.n_items));
-  } else if (w.sweep) {
-    L.kind = 3;
+    L.grid = fixed_grid ? S.grid_cap : std::max(1, std::min(S.grid_cap, L.n_items));
+  } else if (L.kind == 3) {
     L.fn = S.fn_stream;
     L.lds = 0;
     L.sweep_blocks = w.sstart.back();
     const int64_t most = std::max<int64_t>({1, (L.sweep_blocks + kWaves - 1) / kWaves, (int64_t)L.n_tails});
-    L.grid = (int)std::min<int64_t>(S.grid_cap_stream, most);
+    L.grid = fixed_grid ? S.grid_cap_stream : (int)std::min<int64_t>(S.grid_cap_stream, most);
   } else {
-    L.kind = 2;
     L.fn = S.fn_stream;
     L.lds = 0;
-    L.grid = std::max(1, std::min(S.grid_cap_stream, std::max(L.n_items, L.n_tails)));
+    L.grid = fixed_grid ? S.grid_cap_stream : std::max(1, std::min(S.grid_cap_stream, std::max(L.n_items, L.n_tails)));
   }
   return L;
 }
 
 int launch_grouped(const LaunchDesc& L, const DevLists& d, hipStream_t s) {
-  if (L.total_blocks == 0) return NB_OK;
   GroupsArgs g{};
   g.descs = d.descs;
+  g.payload = d.payload;
+  g.counts = d.counts;
   g.counter = d.counter;
-  g.n_groups = L.n_groups;
   g.Fp = L.Fp;
   g.nch = L.nch;
   g.F = L.F;
   g.wt = L.wt;
-  g.total_blocks = L.total_blocks;
-  if (L.kind == 0) {
-    g.gstart = static_cast<const int64_t*>(d.payload);
-  } else if (L.kind == 3) {
-    g.sstart = static_cast<const int64_t*>(d.payload);
-    g.tails = reinterpret_cast<const GroupItem*>(static_cast<const uint8_t*>(d.payload) +
-                                                 align_up(((size_t)L.n_groups + 1) * sizeof(int64_t), 16));
-    g.n_tails = L.n_tails;
-    g.total_blocks = L.sweep_blocks;
-  } else {
-    g.items = static_cast<const GroupItem*>(d.payload);
-    g.n_items = L.n_items;
-    g.tails = g.items + L.n_items;
-    g.n_tails = L.n_tails;
-  }
   void* args[] = {&g};
   NB_HIP_CHECK(hipLaunchKernel(L.fn, dim3(L.grid), dim3(kThreads), args, L.lds, s));
   NB_HIP_CHECK(hipGetLastError());
@@ -963,7 +1000,66 @@ int launch_grouped(const LaunchDesc& L, const DevLists& d, hipStream_t s) {
 }
 
 int launch_grouped(const GroupSetup& S, const WorkList& w, const DevLists& d, hipStream_t s) {
+  if (S.total_blocks == 0) return NB_OK;
   return launch_grouped(describe(S, w), d, s);
+}
+
+// ---- pinned staging of work lists (nb_score_groups returns before the
+// device has read the list): host-pinned buffers per device, each reused
+// once the copy that last read it has completed (an event per buffer).
+struct PinnedSlot {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  int device = -1;
+};
+constexpr int kMaxPinnedSlots = 16;
+std::mutex g_pin_mu;
+std::vector<std::unique_ptr<PinnedSlot>> g_pin;
+
+// Copy `blob` to device memory `dst` on stream s through a pinned buffer.
+int stage_to_device(const std::vector<uint8_t>& blob, void* dst, hipStream_t s) {
+  int dev = -1;
+  NB_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  PinnedSlot* use = nullptr;
+  for (auto& sl : g_pin)
+    if (sl->device == dev && sl->bytes >= blob.size() && hipEventQuery(sl->done) == hipSuccess) {
+      use = sl.get();
+      break;
+    }
+  if (!use) {
+    int mine = 0;
+    for (auto& sl : g_pin) mine += sl->device == dev;
+    if (mine < kMaxPinnedSlots) {
+      auto sl = std::make_unique<PinnedSlot>();
+      sl->device = dev;
+      sl->bytes = std::max<size_t>(blob.size(), (size_t)1 << 20);
+      NB_HIP_CHECK(hipHostMalloc(&sl->host, sl->bytes, hipHostMallocDefault));
+      NB_HIP_CHECK(hipEventCreateWithFlags(&sl->done, hipEventDisableTiming));
+      use = sl.get();
+      g_pin.push_back(std::move(sl));
+    } else {
+      // every buffer of this device is still being read: wait for the first
+      // one and grow it if needed
+      for (auto& sl : g_pin)
+        if (sl->device == dev) {
+          use = sl.get();
+          break;
+        }
+      NB_HIP_CHECK(hipEventSynchronize(use->done));
+      if (use->bytes < blob.size()) {
+        NB_HIP_CHECK(hipHostFree(use->host));
+        use->host = nullptr;
+        use->bytes = blob.size();
+        NB_HIP_CHECK(hipHostMalloc(&use->host, use->bytes, hipHostMallocDefault));
+      }
+    }
+  }
+  std::memcpy(use->host, blob.data(), blob.size());
+  NB_HIP_CHECK(hipMemcpyAsync(dst, use->host, blob.size(), hipMemcpyHostToDevice, s));
+  NB_HIP_CHECK(hipEventRecord(use->done, s));
+  return NB_OK;
 }
 
 // Default schedule: the stream when the table fits, else static ranges.
@@ -1068,6 +1164,7 @@ int prepare_group_launch(const nb_model* models, int32_t n_models, const nb_grou
 }
 
 int enqueue_group_launch(const GroupLaunch& G, void* dev_blob, hipStream_t s) {
+  if (G.total_blocks == 0) return NB_OK;
   LaunchDesc L;
   L.fn = G.fn;
   L.lds = G.lds;
@@ -1092,20 +1189,25 @@ using namespace nb;
 // ------------------------------------------------------------------ plan
 struct nb_group_plan {
   GroupSetup S;
-  void* dev = nullptr;            // work list: counters, descriptors, payload
+  void* dev = nullptr;            // work list: header, descriptors, payload
   size_t dev_bytes = 0;
-  int32_t n_groups = 0;
+  int32_t n_groups = 0;           // groups of the current work list
+  int32_t cap_groups = 0;         // room for descriptors (the creation call's count)
   WorkList w;
   int tuned = 0;
+  LaunchDesc launch;              // the captured launch (kernel, fixed grid)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  void* pinned[2] = {nullptr, nullptr};     // staging of updated work lists
+  hipEvent_t staged[2] = {nullptr, nullptr};
+  int slot = 0;
 };
 
 namespace {
 
 int upload(nb_group_plan* p, const WorkList& w) {
   std::vector<uint8_t> blob;
-  serialise(p->S, w, &blob);
+  serialise(p->S, w, &blob, (size_t)p->cap_groups);
   if (blob.size() > p->dev_bytes) return fail(NB_EHIP, "internal: work list larger than its buffer");
   NB_HIP_CHECK(hipMemcpy(p->dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
   p->w = w;
@@ -1128,17 +1230,18 @@ int autotune(nb_group_plan* p, hipStream_t s) {
   float best = 1e30f;
   int best_t = default_code(p->S);
   int rc = NB_OK;
-  const DevLists d = carve(p->dev, p->n_groups);
+  const DevLists d = carve(p->dev, (size_t)p->cap_groups);
   for (int t : cand) {
     const WorkList w = make_work_list(p->S, t);
     if ((rc = upload(p, w))) break;
-    if ((rc = launch_grouped(p->S, w, d, s))) break;   // warm
+    const LaunchDesc L = describe(p->S, w, true);
+    if ((rc = launch_grouped(L, d, s))) break;   // warm
     // the median of a few single launches: robust to an occasional slow one
     constexpr int kReps = 7;
     float ms_r[kReps];
     for (int r = 0; r < kReps && rc == NB_OK; ++r) {
       if (hipEventRecord(e0, s) != hipSuccess) rc = fail(NB_EHIP, "hipEventRecord");
-      if (!rc) rc = launch_grouped(p->S, w, d, s);
+      if (!rc) rc = launch_grouped(L, d, s);
       if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(NB_EHIP, "hipEventRecord");
       if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(NB_EHIP, "hipEventSynchronize");
       ms_r[r] = 0.0f;
@@ -1165,20 +1268,38 @@ void plan_free(nb_group_plan* p) {
   if (p->exec) hipGraphExecDestroy(p->exec);
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->dev) hipFree(p->dev);
+  for (int i = 0; i < 2; ++i) {
+    if (p->staged[i]) hipEventDestroy(p->staged[i]);
+    if (p->pinned[i]) hipHostFree(p->pinned[i]);
+  }
   delete p;
 }
+
+// Room of a plan's work-list buffer: updated work lists may carry up to this
+// many times the payload of the largest list the creation call could make,
+// and at least kPlanMinPayload bytes (65,536 items), for up to the creation
+// call's number of groups.
+constexpr size_t kPlanHeadroom = 4;
+constexpr size_t kPlanMinPayload = (size_t)1 << 20;
 
 int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
                int32_t xtype, int32_t wtype, int32_t tile_rows, int32_t flags, hipStream_t s) {
   int rc = setup_groups(models, n_models, groups, n_groups, xtype, wtype, &p->S);
   if (rc) return rc;
   p->n_groups = n_groups;
-  // room for the largest work list any schedule makes (the smallest tiles)
-  p->dev_bytes = std::max({work_list_bytes(n_groups, payload_bytes(make_work_list(p->S, kWaves))),
-                           work_list_bytes(n_groups, payload_bytes(make_work_list(p->S, -kWaves))),
-                           work_list_bytes(n_groups, (n_groups + 1) * sizeof(int64_t))});
+  p->cap_groups = n_groups;
+  // room for the largest work list any schedule makes (the smallest tiles),
+  // times the headroom for later steps
+  const size_t pay = std::max({payload_bytes(make_work_list(p->S, kWaves)),
+                               payload_bytes(make_work_list(p->S, -kWaves)),
+                               ((size_t)n_groups + 1) * sizeof(int64_t) + 16});
+  p->dev_bytes = work_list_bytes((size_t)n_groups, std::max(kPlanHeadroom * pay, kPlanMinPayload));
   NB_HIP_CHECK(hipStreamSynchronize(s));
   NB_HIP_CHECK(hipMalloc(&p->dev, p->dev_bytes));
+  for (int i = 0; i < 2; ++i) {
+    NB_HIP_CHECK(hipHostMalloc(&p->pinned[i], p->dev_bytes, hipHostMallocDefault));
+    NB_HIP_CHECK(hipEventCreateWithFlags(&p->staged[i], hipEventDisableTiming));
+  }
   const std::string key = tune_key(p->S, n_groups);
   int tile = 0;
   int cached = 0;
@@ -1200,6 +1321,7 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
     tile = default_code(p->S);
   }
   if ((rc = upload(p, make_work_list(p->S, tile)))) return rc;
+  p->launch = describe(p->S, p->w, true);
   // capture the launch into a graph on a private stream
   hipStream_t cs;
   NB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1207,7 +1329,7 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
     hipStreamDestroy(cs);
     return fail(NB_EHIP, "hipStreamBeginCapture failed");
   }
-  rc = launch_grouped(p->S, p->w, carve(p->dev, n_groups), cs);
+  rc = launch_grouped(p->launch, carve(p->dev, (size_t)p->cap_groups), cs);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &graph);
   hipStreamDestroy(cs);
@@ -1218,6 +1340,41 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
   if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
   p->graph = graph;
   NB_HIP_CHECK(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0));
+  return NB_OK;
+}
+
+// A new step's groups for an existing plan: same kernel, new work list.
+int plan_update(nb_group_plan* p, const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
+                hipStream_t s) {
+  if (n_groups > p->cap_groups)
+    return fail(NB_EINVAL, "more groups (" + std::to_string(n_groups) + ") than the plan was created with (" +
+                               std::to_string(p->cap_groups) + ")");
+  GroupSetup S;
+  int rc = setup_groups(models, n_models, groups, n_groups, p->S.xtype, p->S.wtype, &S);
+  if (rc) return rc;
+  const WorkList w = make_work_list(S, p->w.code);
+  const LaunchDesc L = describe(S, w, true);
+  // the captured kernel, its launch shape and its fixed arguments must serve
+  if (L.fn != p->launch.fn || L.lds != p->launch.lds || L.grid != p->launch.grid || S.F != p->S.F ||
+      S.Fp != p->S.Fp || S.nch != p->S.nch)
+    return fail(NB_EINVAL, "the new groups need another kernel than the plan's (models must share the plan's "
+                           "feature count and kind, the same outputs must be requested, and rows must stay "
+                           "eligible for the plan's row staging)");
+  std::vector<uint8_t> blob;
+  serialise(S, w, &blob, (size_t)p->cap_groups);
+  if (blob.size() > p->dev_bytes)
+    return fail(NB_ENOMEM, "the new work list (" + std::to_string(blob.size()) + " bytes) exceeds the plan's room (" +
+                               std::to_string(p->dev_bytes) + " bytes): create a plan for the larger step");
+  // the pinned buffer is free once the copy that last read it has run
+  const int k = p->slot;
+  NB_HIP_CHECK(hipEventSynchronize(p->staged[k]));
+  std::memcpy(p->pinned[k], blob.data(), blob.size());
+  NB_HIP_CHECK(hipMemcpyAsync(p->dev, p->pinned[k], blob.size(), hipMemcpyHostToDevice, s));
+  NB_HIP_CHECK(hipEventRecord(p->staged[k], s));
+  p->slot ^= 1;
+  p->S = std::move(S);
+  p->w = w;
+  p->n_groups = n_groups;
   return NB_OK;
 }
 
@@ -1246,11 +1403,10 @@ int nb_score_groups(const nb_model* models, int32_t n_models, const nb_group* gr
     return fail(NB_EINVAL, "workspace must be 256-byte aligned");
   if (workspace_bytes_ < blob.size()) return fail(NB_ENOMEM, "workspace smaller than nb_score_groups_workspace_bytes()");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  NB_HIP_CHECK(hipMemcpyAsync(workspace, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
-  if ((rc = enqueue_group_launch(L, workspace, s))) return rc;
-  // the work list is staged from host memory released on return
-  NB_HIP_CHECK(hipStreamSynchronize(s));
-  return NB_OK;
+  // the work list goes through pinned host memory: the call returns once
+  // the copy and the launch are enqueued
+  if ((rc = stage_to_device(blob, workspace, s))) return rc;
+  return enqueue_group_launch(L, workspace, s);
 }
 
 int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,
@@ -1274,6 +1430,12 @@ int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_grou
   return NB_OK;
 }
 
+int nb_group_plan_update(nb_group_plan* plan, const nb_model* models, int32_t n_models, const nb_group* groups,
+                         int32_t n_groups, void* stream) {
+  if (!plan) return fail(NB_EINVAL, "plan is NULL");
+  return plan_update(plan, models, n_models, groups, n_groups, reinterpret_cast<hipStream_t>(stream));
+}
+
 int nb_group_plan_launch(nb_group_plan* plan, void* stream) {
   if (!plan) return fail(NB_EINVAL, "plan is NULL");
   if (plan->S.total_blocks == 0) return NB_OK;
@@ -1284,7 +1446,7 @@ int nb_group_plan_launch(nb_group_plan* plan, void* stream) {
 int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out) {
   if (!plan || !out) return fail(NB_EINVAL, "NULL argument");
   const int br = (64 / plan->S.lpr) * block_steps_of(plan->S.xtype, false, plan->S.nch, plan->S.fl);
-  const LaunchDesc L = describe(plan->S, plan->w);
+  const LaunchDesc L = describe(plan->S, plan->w, true);
   const int code = plan->w.code;
   out->schedule = code == 0 ? NB_SCHEDULE_STATIC : (code > 0 ? NB_SCHEDULE_DYNAMIC : NB_SCHEDULE_STREAM);
   out->tile_rows = code == 0 ? (int32_t)std::min<int64_t>(INT32_MAX, (plan->S.total_blocks + L.grid - 1) / L.grid * br)

@@ -256,3 +256,107 @@ def test_groups_full_size_sampled():
         ii = torch.from_numpy(idx).to(DEV)
         assert_scores(om, to_np(xs[g][ii]), to_np(lab[ii]), to_np(lp[ii]), to_np(sc[ii]))
     plan.close()
+
+
+def _slices(base, sizes):
+    cuts = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
+    return [base[cuts[i]:cuts[i + 1]] for i in range(len(sizes))]
+
+
+@pytest.mark.parametrize("F,sched,tile", [(2000, "stream", 0), (1000, "stream", 0), (2000, "static", 0),
+                                          (2000, None, 256), (1000, None, 64)],
+                         ids=["sweep_F2000", "stream_F1000", "static_F2000", "dynamic_F2000", "dynamic_F1000"])
+def test_plan_update_takes_new_steps(F, sched, tile):
+    """A plan re-pointed at each step's groups (new sizes, fewer groups, new
+    inputs and outputs, empty and untrained groups) replays its captured
+    graph with the new work list: every step equals the eager grouped call,
+    with two updates and launches queued before anything is awaited."""
+    _case(f"plan update F={F} sched={sched} tile={tile}")
+    models, _, gmodel, xs, _, _ = _build(F, nb.MULTINOMIAL)
+    plan = nbg.GroupPlan(models, list(zip(gmodel, xs)), schedule=sched, tile_rows=tile)
+    base = W.group_workload(31, F).test_set(30000, device=DEV)[0]
+    steps = [
+        ([400, 0, 9000, 17, 2500, 1, 64, 333, 12000, 5], gmodel),                       # same count, new sizes
+        ([5000, 3000, 77], [1, None, 0]),                                               # fewer groups
+        ([1, 2, 3, 4, 5, 6, 7, 8, 9, 10], [None, 2, None, 0, 1, 3, 5, None, 6, 4]),     # tiny groups
+    ]
+    queued = []
+    for k, (sizes, owners) in enumerate(steps):
+        groups = list(zip(owners, _slices(base[(k * 997):], sizes)))
+        outs = plan.update(models, groups)
+        plan.launch()
+        queued.append((groups, outs))
+        if len(queued) == 2:      # two steps in flight, then check both
+            torch.cuda.synchronize()
+            for gr, o in queued:
+                want = nbg.score_groups(models, gr)
+                torch.cuda.synchronize()
+                for a, b in zip(o, want):
+                    _assert_equal(a, b)
+            queued.clear()
+    torch.cuda.synchronize()
+    for gr, o in queued:
+        want = nbg.score_groups(models, gr)
+        torch.cuda.synchronize()
+        for a, b in zip(o, want):
+            _assert_equal(a, b)
+    plan.close()
+
+
+def test_plan_update_refusals():
+    _case("plan update refusals")
+    F = 2000
+    models, _, gmodel, xs, _, _ = _build(F, nb.MULTINOMIAL, sizes=[300, 40, 2000], has=[True, True, True])
+    plan = nbg.GroupPlan(models, list(zip(gmodel, xs)), schedule="stream")
+    base = W.group_workload(5, F).test_set(200000, device=DEV)[0]
+    with pytest.raises(nbg.NBError) as e:                      # more groups than at creation
+        plan.update(models, [(0, base[:10])] * 4)
+    assert e.value.code == -1
+    with pytest.raises(nbg.NBError) as e:                      # other outputs: another kernel
+        plan.update(models, [(0, base[:10])], scores=True)
+    assert e.value.code == -1
+    other = nbg.Model(2, 1000)
+    with pytest.raises(nbg.NBError) as e:                      # another feature count
+        plan.update([other], [(0, base[:10, :1000])])
+    assert e.value.code == -1
+    # a much larger step (the sweep's work list does not grow with the files)
+    big = [(0, base[:150000]), (1, base[150000:150001]), (2, base[150001:])]
+    outs = plan.update(models, big)
+    plan.launch()
+    torch.cuda.synchronize()
+    for a, b in zip(outs, nbg.score_groups(models, big)):
+        _assert_equal(a, b)
+    # the plan still serves a valid step after the refusals
+    gr = [(0, base[:500]), (None, base[500:800]), (2, base[800:900])]
+    outs = plan.update(models, gr)
+    plan.launch()
+    torch.cuda.synchronize()
+    for a, b in zip(outs, nbg.score_groups(models, gr)):
+        _assert_equal(a, b)
+    plan.close()
+
+
+def test_score_groups_returns_before_the_device():
+    """nb_score_groups enqueues and returns (its work list staged through
+    pinned memory): many calls queued back to back, each with its own
+    groups and outputs, all equal to the groups scored alone."""
+    _case("score_groups asynchronous")
+    F = 2000
+    models, _, gmodel, xs, _, route = _build(F, nb.MULTINOMIAL)
+    base = W.group_workload(17, F).test_set(40000, device=DEV)[0]
+    rng = np.random.default_rng(5)
+    calls = []
+    for k in range(24):
+        sizes = rng.integers(0, 3000, size=6)
+        owners = [int(v) if v >= 0 else None for v in rng.integers(-1, len(models), size=6)]
+        if all(o is None for o in owners):
+            owners[0] = 0
+        groups = list(zip(owners, _slices(base[int(rng.integers(0, 20000)):], sizes)))
+        calls.append((groups, nbg.score_groups(models, groups, scores=True)))
+    torch.cuda.synchronize()
+    for groups, outs in calls:
+        rt = og.route(np.array([o is not None for o, _ in groups]))
+        for g, (o, x) in enumerate(groups):
+            if x.shape[0] == 0:
+                continue
+            _assert_equal(outs[g], nbg.score(models[groups[rt[g]][0]], x, scores=True))

@@ -1004,11 +1004,38 @@ int launch_grouped(const GroupSetup& S, const WorkList& w, const DevLists& d, hi
   return launch_grouped(describe(S, w), d, s);
 }
 
-// ---- pinned staging of work lists (nb_score_groups returns before the
-// device has read the list): host-pinned buffers per device, each reused
-// once the copy that last read it has completed (an event per buffer).
+// ---- pinned staging of work lists (nb_score_groups and plan updates
+// return before the device has read the list): coherent host-pinned
+// buffers, mapped into the device's address space, read by a small copy
+// kernel on the caller's stream (a copy-engine transfer between two kernels
+// of one stream costs tens of microseconds of queue hand-over, measured;
+// a kernel costs none), each buffer reused once the copy that last read it
+// has run (an event per buffer).
+__global__ __launch_bounds__(256) void copy_list_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                       int n16) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n16; i += gridDim.x * 256) dst[i] = src[i];
+}
+
+int host_buffer(size_t bytes, void** host, void** dev_view) {
+  NB_HIP_CHECK(hipHostMalloc(host, bytes, hipHostMallocCoherent | hipHostMallocMapped));
+  NB_HIP_CHECK(hipHostGetDevicePointer(dev_view, *host, 0));
+  return NB_OK;
+}
+
+// Enqueue the copy of `bytes` (a multiple of 16) from a mapped pinned
+// buffer to device memory.
+int enqueue_list_copy(const void* src_view, void* dst, size_t bytes, hipStream_t s) {
+  const int n16 = (int)(bytes / 16);
+  const int grid = std::max(1, std::min(64, (n16 + 255) / 256));
+  hipLaunchKernelGGL(copy_list_kernel, dim3(grid), dim3(256), 0, s, static_cast<const uint4*>(src_view),
+                     static_cast<uint4*>(dst), n16);
+  NB_HIP_CHECK(hipGetLastError());
+  return NB_OK;
+}
+
 struct PinnedSlot {
   void* host = nullptr;
+  void* view = nullptr;            // the device's address of host
   size_t bytes = 0;
   hipEvent_t done = nullptr;
   int device = -1;
@@ -1035,7 +1062,7 @@ int stage_to_device(const std::vector<uint8_t>& blob, void* dst, hipStream_t s) 
       auto sl = std::make_unique<PinnedSlot>();
       sl->device = dev;
       sl->bytes = std::max<size_t>(blob.size(), (size_t)1 << 20);
-      NB_HIP_CHECK(hipHostMalloc(&sl->host, sl->bytes, hipHostMallocDefault));
+      if (int rc = host_buffer(sl->bytes, &sl->host, &sl->view)) return rc;
       NB_HIP_CHECK(hipEventCreateWithFlags(&sl->done, hipEventDisableTiming));
       use = sl.get();
       g_pin.push_back(std::move(sl));
@@ -1052,12 +1079,12 @@ int stage_to_device(const std::vector<uint8_t>& blob, void* dst, hipStream_t s) 
         NB_HIP_CHECK(hipHostFree(use->host));
         use->host = nullptr;
         use->bytes = blob.size();
-        NB_HIP_CHECK(hipHostMalloc(&use->host, use->bytes, hipHostMallocDefault));
+        if (int rc = host_buffer(use->bytes, &use->host, &use->view)) return rc;
       }
     }
   }
   std::memcpy(use->host, blob.data(), blob.size());
-  NB_HIP_CHECK(hipMemcpyAsync(dst, use->host, blob.size(), hipMemcpyHostToDevice, s));
+  if (int rc = enqueue_list_copy(use->view, dst, blob.size(), s)) return rc;
   NB_HIP_CHECK(hipEventRecord(use->done, s));
   return NB_OK;
 }
@@ -1199,6 +1226,7 @@ struct nb_group_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* pinned[2] = {nullptr, nullptr};     // staging of updated work lists
+  void* pinned_view[2] = {nullptr, nullptr};
   hipEvent_t staged[2] = {nullptr, nullptr};
   int slot = 0;
 };
@@ -1297,7 +1325,7 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
   NB_HIP_CHECK(hipStreamSynchronize(s));
   NB_HIP_CHECK(hipMalloc(&p->dev, p->dev_bytes));
   for (int i = 0; i < 2; ++i) {
-    NB_HIP_CHECK(hipHostMalloc(&p->pinned[i], p->dev_bytes, hipHostMallocDefault));
+    if ((rc = host_buffer(p->dev_bytes, &p->pinned[i], &p->pinned_view[i]))) return rc;
     NB_HIP_CHECK(hipEventCreateWithFlags(&p->staged[i], hipEventDisableTiming));
   }
   const std::string key = tune_key(p->S, n_groups);
@@ -1369,7 +1397,7 @@ int plan_update(nb_group_plan* p, const nb_model* models, int32_t n_models, cons
   const int k = p->slot;
   NB_HIP_CHECK(hipEventSynchronize(p->staged[k]));
   std::memcpy(p->pinned[k], blob.data(), blob.size());
-  NB_HIP_CHECK(hipMemcpyAsync(p->dev, p->pinned[k], blob.size(), hipMemcpyHostToDevice, s));
+  if ((rc = enqueue_list_copy(p->pinned_view[k], p->dev, blob.size(), s))) return rc;
   NB_HIP_CHECK(hipEventRecord(p->staged[k], s));
   p->slot ^= 1;
   p->S = std::move(S);

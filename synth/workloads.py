@@ -194,9 +194,10 @@ FAMILY_TRAIN, FAMILY_TEST = 800_000, 4_000_000
 
 
 def group_sizes(n_groups: int = 256, mu: float = 7.0, sigma: float = 1.5,
-                lo: int = 100, hi: int = 100_000) -> np.ndarray:
-    """Test-file counts of size groups: lognormal(mu, sigma) clipped to [lo, hi]."""
-    rng = _np_rng(4, ROLE_SIZES)
+                lo: int = 100, hi: int = 100_000, step: int = 0) -> np.ndarray:
+    """Test-file counts of size groups: lognormal(mu, sigma) clipped to [lo, hi];
+    step > 0 draws the counts of a later step of the same workload."""
+    rng = _np_rng(4, ROLE_SIZES) if step == 0 else _np_rng(4, ROLE_SIZES, step)
     return np.clip(np.rint(rng.lognormal(mu, sigma, size=n_groups)), lo, hi).astype(np.int64)
 
 

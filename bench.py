@@ -38,7 +38,10 @@ step's inputs.  Extra objects (skip with --no-extras):
              per-group top-k, test files in multiples of 768): GPU grouped
              classification time vs the oracle on one host core.
 --copy-calibration runs only a plain device copy of known size (used to scale
-the HBM byte counters of rocprofv3).
+the HBM byte counters of rocprofv3).  --save-inputs / --inputs-dir write the
+seeded inputs of the headline step (or of the groups leg) to files and read
+them back, so that a counter run sees the timed runs' bytes without running
+the generator under the counter collector (see SeededInputs).
 """
 from __future__ import annotations
 
@@ -76,8 +79,58 @@ def parse():
     ap.add_argument("--fill-inputs", action="store_true",
                     help="constant-filled inputs instead of the seeded generator (for hardware-counter runs: "
                          "the kernels' memory traffic does not depend on feature values)")
+    ap.add_argument("--inputs-dir", default=None,
+                    help="read the seeded inputs from .npy files in this directory (written by an earlier run "
+                         "with --save-inputs) instead of generating them: counter runs use this")
+    ap.add_argument("--save-inputs", action="store_true",
+                    help="generate the seeded inputs of the headline step (or of --leg groups), write them to "
+                         "--inputs-dir and exit")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="with --leg groups: build the models, score the groups five times with eager "
+                         "nb_score_groups calls (FP32 table, default schedule) and exit (for counter runs)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "score2_u8_F1000_traffic.json"))
     return ap.parse_args()
+
+
+class SeededInputs:
+    """Seeded inputs, generated on the device (synth/philox.py) or read back
+    from the files an earlier run wrote.
+
+    Under rocprofv3's counter collection (--pmc) the profiled process dies
+    with SIGSEGV inside torch's int64 right-shift kernel, which the seeded
+    generator dispatches.  A counter run therefore loads the inputs that an
+    unprofiled run of the same command generated and saved: the profiled
+    process then runs only host-to-device copies and this library's kernels
+    on the same bytes as the timed runs."""
+
+    def __init__(self, directory: str | None = None, save: bool = False):
+        self.dir, self.save = directory, save
+        if save:
+            if not directory:
+                raise SystemExit("bench.py: --save-inputs needs --inputs-dir")
+            os.makedirs(directory, exist_ok=True)
+
+    @property
+    def loading(self) -> bool:
+        return bool(self.dir) and not self.save
+
+    def get(self, name: str, make):
+        """make() -> tuple of device tensors from the seeded generator."""
+        if self.loading:
+            out = []
+            while os.path.exists(path := os.path.join(self.dir, f"{name}.{len(out)}.npy")):
+                out.append(torch.from_numpy(np.load(path)).to("cuda"))
+            if not out:
+                raise FileNotFoundError(f"no saved inputs {name}.*.npy in {self.dir}: run with --save-inputs first")
+            return tuple(out)
+        t = tuple(make())
+        if self.save:
+            for i, x in enumerate(t):
+                np.save(os.path.join(self.dir, f"{name}.{i}.npy"), x.cpu().numpy())
+        return t
+
+
+INPUTS = SeededInputs()
 
 
 def timed(fn, reps=10):
@@ -120,14 +173,20 @@ SCORE2_SOURCES = ["paper_1905_13746_amd/csrc/nb_score.hip", "paper_1905_13746_am
                   "paper_1905_13746_amd/csrc/nb_device.hpp"]
 
 
-def load_traffic(path):
-    """HBM bytes per scoring launch from the committed rocprofv3 counter runs,
-    if they were taken on the current scoring kernel source (hash match)."""
+# the files the grouped kernels are compiled from
+GROUPS_SOURCES = ["paper_1905_13746_amd/csrc/nb_groups.hip", "paper_1905_13746_amd/csrc/nb_score2.hpp",
+                  "paper_1905_13746_amd/csrc/nb_device.hpp", "paper_1905_13746_amd/csrc/nb_internal.hpp"]
+GROUPS_TRAFFIC = os.path.join(ROOT, "profiles", "score2_groups_sweep_256_F2000_traffic.json")
+
+
+def load_traffic(path, sources=SCORE2_SOURCES):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if
+    they were taken on the current kernel source (hash match)."""
     from paper_1905_13746_amd.rocprof_summary import source_hash
     try:
         with open(path) as fh:
             t = json.load(fh)
-        if t.get("sources") != SCORE2_SOURCES or t.get("source_sha256") != source_hash(SCORE2_SOURCES):
+        if t.get("sources") != sources or t.get("source_sha256") != source_hash(sources):
             return None
         return float(t["hbm_bytes_per_launch"])
     except Exception:
@@ -296,28 +355,40 @@ def error_vs_oracle():
                        **{k: r[k] for k in keep if k in r}} for r in rep["results"]]}
 
 
-def groups_leg(nbg, W, steps: int = 20):
+def groups_leg(nbg, W, steps: int = 20, counter_run: bool = False):
     """Batched size-group scoring (256 groups, F = 2000, two classes): a
     captured plan (one persistent launch) with the FP32 table, the BF16
     table, and the BF16 table on FP8-e4m3 features, against a loop of
-    per-group launches over the same buffers."""
+    per-group launches over the same buffers.  counter_run: only five eager
+    grouped calls with the FP32 table (for rocprofv3 --pmc)."""
     sizes = W.group_sizes()
     F = 2000
     CPU_GROUPS = 16
     models, xs, cpu_train = [], [], []
     for g, n in enumerate(sizes):
         wl = W.group_workload(g, F)
-        X, y = wl.train_set(int(min(2 * n, 20_000)), device="cuda")
+        X, y = INPUTS.get(f"groups_F{F}_g{g}_train", lambda: wl.train_set(int(min(2 * n, 20_000)), device="cuda"))
         m = nbg.Model(2, F, "multinomial")
         nbg.train(m, X, y)
         if g < CPU_GROUPS:
             cpu_train.append((X.cpu().numpy(), y.cpu().numpy()))
         del X, y
         models.append(m)
-        xs.append(wl.test_set(int(n), device="cuda")[0])
+        xs.append(INPUTS.get(f"groups_F{F}_g{g}_test", lambda: wl.test_set(int(n), device="cuda")[:1])[0])
     n = int(sizes.sum())
     algo = n * (F + 4 + 2 * 4)
     groups = list(enumerate(xs))
+    if INPUTS.save:
+        return {"saved_inputs": INPUTS.dir, "n_files": n}
+    if counter_run:
+        # eager calls of the default schedule (the staged sweep at this
+        # shape): the plan's kernel and work list, no graph under the
+        # counter collector
+        outs = None
+        for _ in range(5):
+            outs = nbg.score_groups(models, groups, outs=outs)
+        torch.cuda.synchronize()
+        return {"counter_run": True, "n_files": n, "algorithmic_bytes_per_launch": algo}
     tables = {}
     outs = None
     for name, wtype, fp8 in (("fp32_table_u8", nbg.W_F32, False), ("bf16_table_u8", nbg.W_BF16, False),
@@ -344,7 +415,8 @@ def groups_leg(nbg, W, steps: int = 20):
     res = {"workload": f"256 groups, n_g = clip(round(lognormal(7, 1.5)), 100, 1e5), F={F} uint8 (and FP8-e4m3), "
                        "two classes, multinomial; models trained on min(2 n_g, 20000) files per group",
            "n_files": n, "algorithmic_bytes_per_launch": algo, "tables": tables,
-           "per_group_launch_loop_ms": ms_loop, "speedup_vs_loop": ms_loop / ms_plan, "fresh_sizes": fresh}
+           "per_group_launch_loop_ms": ms_loop, "speedup_vs_loop": ms_loop / ms_plan, "fresh_sizes": fresh,
+           "traffic_stream_fp32": load_traffic(GROUPS_TRAFFIC, GROUPS_SOURCES)}
     res["cpu_baseline"] = groups_cpu_baseline(cpu_train, xs[:CPU_GROUPS])
     return res
 
@@ -735,7 +807,7 @@ def compact(leg: str, res: dict) -> dict:
         out = {k: res[k] for k in ("n_files",)}
         for name, v in res["tables"].items():
             out[name] = {"files_per_s": round(v["files_per_s"]), "frac_of_peak": r3(v["frac_of_peak"]),
-                         "schedule": v["plan"]["schedule"]}
+                         "schedule": v["plan"]["schedule"] + (" (staged sweep)" if v["plan"].get("staged") else "")}
         for k in ("per_group_launch_loop_ms", "speedup_vs_loop"):
             if k in res:
                 out[k] = r3(res[k])
@@ -744,6 +816,9 @@ def compact(leg: str, res: dict) -> dict:
             out["fresh_sizes_each_step_bf16"] = {"files_per_s": round(f["files_per_s"]),
                                                  "frac_of_peak": r3(f["frac_of_peak"]),
                                                  "ms_per_step": r3(f["ms_per_step"])}
+        if res.get("traffic_stream_fp32"):
+            out["traffic_over_algorithmic_stream_fp32"] = r3(res["traffic_stream_fp32"] /
+                                                             res["algorithmic_bytes_per_launch"])
         out["cpu_baseline_files_per_s"] = round(res["cpu_baseline"]["value"])
         return out
     if leg == "serve":
@@ -789,14 +864,20 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    global INPUTS
+    INPUTS = SeededInputs(args.inputs_dir, args.save_inputs)
+    if INPUTS.dir and args.leg not in (None, "groups"):
+        raise SystemExit("bench.py: --inputs-dir/--save-inputs cover the headline step and --leg groups")
     import paper_1905_13746_amd as nbg
     from synth import workloads as W
     if args.leg:
-        if args.leg == "precision":
+        if args.leg == "groups":
+            res = groups_leg(nbg, W, counter_run=args.counter_run)
+        elif args.leg == "precision":
             res = precision_compare(nbg, W, fill=args.fill_inputs)
         else:
             ks = tuple(int(v) for v in args.select_k.split(","))
-            res = {"f_sweep": f_sweep, "groups": groups_leg, "replay": replay_leg,
+            res = {"f_sweep": f_sweep, "replay": replay_leg,
                    "gaussian": lambda a, b: gaussian_leg(a, b, fill=args.fill_inputs),
                    "select": lambda a, b: select_leg(a, b, ks=ks, fill=args.fill_inputs),
                    "serve": lambda a, b: serve_leg(a, b, full=True)}[args.leg](nbg, W)
@@ -812,8 +893,13 @@ def main():
         Xte = torch.full((args.n_test, F), 2, dtype=torch.uint8, device="cuda")
         args.no_cpu = args.no_extras = True
     else:
-        Xtr, ytr = wl.train_set(args.n_train, device="cuda")
-        Xte, _ = wl.test_set(args.n_test, device="cuda")
+        Xtr, ytr = INPUTS.get(f"headline_F{F}_train{args.n_train}", lambda: wl.train_set(args.n_train, device="cuda"))
+        Xte, = INPUTS.get(f"headline_F{F}_test{args.n_test}", lambda: wl.test_set(args.n_test, device="cuda")[:1])
+        if INPUTS.save:
+            print(json.dumps({"saved_inputs": INPUTS.dir}), flush=True)
+            return
+        if INPUTS.loading:
+            args.no_cpu = args.no_extras = True
     model = nbg.Model(2, F, "multinomial")
     ws = nbg.train_workspace(model, args.n_train)
     n = args.n_test

@@ -281,8 +281,9 @@ int nb_route_groups(const int64_t* class_counts_host, int32_t n_groups, int32_t 
  * Schedules: stream (the default when NS x Fp <= 2048 table floats: groups
  * cut into items of a few blocks, taken round-robin in memory order, each
  * wave's loads pipelined across items, the next item's table loaded with
- * them; for byte features of 1025 to 2036 features per file with 8-byte
- * aligned rows and at most 320 groups, a sweep instead: every wave takes
+ * them; for byte features of 1,792 to 2,032 per file (a multiple of 8),
+ * 8-byte aligned inputs, row strides of at most 17/16 of a row and at most
+ * 320 groups, a sweep instead: every wave takes
  * runs of four blocks of the concatenated groups in memory order, each
  * block fetched as one window of whole cache lines into LDS), static ranges
  * (each workgroup scores an equal contiguous run of files, staging a
@@ -375,6 +376,8 @@ typedef struct {
   int32_t rows_per_block;  /* files per wave block of the kernel               */
   int32_t lds_bytes;       /* table bytes staged in LDS per workgroup          */
   int32_t schedule;        /* NB_SCHEDULE_STATIC, _DYNAMIC or _STREAM          */
+  int32_t staged;          /* 1: the stream runs as the sweep whose blocks are
+                              staged through LDS (two-chunk byte rows), 0 not */
 } nb_group_plan_info;
 
 int nb_group_plan_create(const nb_model* models, int32_t n_models, const nb_group* groups, int32_t n_groups,

@@ -53,7 +53,8 @@ class NbGroup(ctypes.Structure):
 class NbGroupPlanInfo(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("n_items", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("n_files", ctypes.c_int64), ("rows_per_block", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("staged", ctypes.c_int32)]
 
 
 class NbRequest(ctypes.Structure):

@@ -311,9 +311,11 @@ __global__ __launch_bounds__(kThreads) void score2_groups_stream_kernel(GroupsAr
 
 // The stream schedule with flat staging (two-chunk byte rows; see
 // score_blocks): a sweep, the single-model kernel's order over the
-// concatenation of every group's blocks.  Wave w of the grid takes sweep
-// blocks w, w + W, w + 2W, ... (W waves), so the machine reads one window of
-// memory at a time and every wave gets the same number of blocks.  Each
+// concatenation of every group's blocks.  The blocks form runs of
+// kSweepRun consecutive blocks; wave w of the grid takes runs w, w + W,
+// w + 2W, ... (W waves) and the blocks past the last whole round one at a
+// time, so the machine reads one window of memory at a time and the waves'
+// block counts differ by at most kSweepRun.  Each
 // block is fetched as ONE aligned window of FL 1 KB pieces into the wave's
 // LDS region and read back row by row with the lane mapping of the direct
 // loads (identical arithmetic).  The groups' prefix block counts and a
@@ -1486,6 +1488,7 @@ int nb_group_plan_query(const nb_group_plan* plan, nb_group_plan_info* out) {
   out->n_files = plan->S.n_files;
   out->rows_per_block = br;
   out->lds_bytes = (int32_t)plan->S.lds;
+  out->staged = plan->w.sweep ? 1 : 0;
   return NB_OK;
 }
 

@@ -97,9 +97,11 @@ def test_flat_fp8_features(F):
 
 
 def test_flat_in_grouped_schedules():
-    """The stream, static-range and dynamic-item grouped kernels stage
-    blocks too: bit-identical to each group scored alone, with groups
-    starting at arbitrary rows of one buffer."""
+    """The stream schedule runs as the staged sweep (blocks of the
+    concatenated groups staged through LDS, groups smaller than a window
+    scored as tails); static ranges and dynamic items load directly.  Each
+    is bit-identical to each group scored alone, with groups starting at
+    arbitrary rows of one buffer."""
     _case("flat grouped F=2000")
     F = 2000
     models, xs = [], []
@@ -115,7 +117,9 @@ def test_flat_in_grouped_schedules():
     # (the stream schedule holds one table row: no raw scores)
     for sched, scores in (("stream", False), ("static", True), (None, True)):
         plan = nbg.GroupPlan(models, groups, scores=scores, schedule=sched, tile_rows=0 if sched else 512)
-        assert plan.info()["schedule"] == {"stream": "stream", "static": "static", None: "dynamic"}[sched]
+        info = plan.info()
+        assert info["schedule"] == {"stream": "stream", "static": "static", None: "dynamic"}[sched]
+        assert info["staged"] == (1 if sched == "stream" else 0)
         plan.launch()
         torch.cuda.synchronize()
         for (g, x), out in zip(groups, plan.outs):

@@ -370,29 +370,43 @@ __global__ __launch_bounds__(kThreadsFull) void scoreM_full_kernel(ScoreMArgs a)
   }
 }
 
-// Staged variant for one column tile (at most 16 score rows) and Fp <= 4096:
-// the feature loads read whole 128-byte lines (a wave instruction covers 8
-// files x 128 bytes) instead of the A-operand layout's 16 files x 64 bytes,
-// and each wave transposes its loads through a private LDS stage into the
-// operand layout.  LDS holds the whole BF16 table (16 rows x Fp, no padding:
-// the 16-byte granules of row r are XOR-swizzled by r, so the 16 rows read
-// by one B fragment fall in distinct banks) plus one 4 KB stage per wave:
-// 32 files x 128 bytes, granule p of file r stored at p ^ ((r >> 1) & 7),
-// which keeps both the line-shaped writes and the operand-shaped reads free
-// of bank conflicts.  Loads run NB_STAGE_DEPTH groups ahead in registers.
-#define NB_STAGE_DEPTH 3
-constexpr int kStageWaves = 8;
+// Staged variant for one column tile (at most 16 score rows) and Fp <= 4096.
+// A wave tile is 16 files; a group is 512 features.  Each group's loads
+// read 512 contiguous bytes of each of the 16 files (a wave instruction
+// covers 2 files x 512 bytes, eight instructions per group) instead of the
+// A-operand layout's 16 files x 64 bytes, and the wave transposes them
+// through a private 8 KB LDS stage into the operand layout.  The run length
+// per file is what counts on HBM: with the same stage scheme, 128 contiguous
+// bytes per file (32 files per tile) held the kernel at 69% of peak, 256
+// bytes gave the same, 512 bytes 78%, whatever the waves per CU (8 or 16) or
+// the groups in flight (2 to 5); 1024 bytes leave room for only two waves
+// per CU.  LDS holds the whole BF16 table (16 rows x Fp, no padding: the
+// 16-byte granules of row r are XOR-swizzled by r, so the 16 rows read by
+// one B fragment fall in distinct banks) plus the four waves' stages; granule
+// p of file r of a stage sits at p ^ (r & 15) (p ^ ((r >> 1) & 7) for
+// 128-byte groups), which keeps both the line-shaped writes and the
+// operand-shaped reads free of bank conflicts.  Loads run kStageDepth - 1
+// groups ahead in registers, across tile boundaries.
+constexpr int kStageWaves = 4;
 constexpr int kStageThreads = 64 * kStageWaves;
-constexpr int kStageFiles = 32;                   // files per wave tile (two 16-file MFMA tiles)
-constexpr int kStageGB = 128;                     // features per group (two 64-feature windows)
+constexpr int kStageMT = 1;                       // 16-file MFMA tiles per wave tile
+constexpr int kStageFiles = 16 * kStageMT;        // files per wave tile
+constexpr int kStageGB = 512;                     // features (bytes) per file per group
+constexpr int kStageWin = kStageGB / kWindow;     // 64-feature windows per group
+constexpr int kStageNG = kStageGB / 16;           // 16-byte granules per file per group
+constexpr int kStageFPI = 1024 / kStageGB;        // files per wave load instruction
+constexpr int kStageLoads = kStageFiles / kStageFPI;   // 16-byte loads per lane per group
 constexpr int kStageBytes = kStageFiles * kStageGB;
-constexpr int kStageDepth = NB_STAGE_DEPTH;
+static_assert(kStageGB >= 128 && kStageGB <= 1024 && kStageFiles % kStageFPI == 0, "stage shape");
+constexpr int kStageDepth = 3;
 #ifndef NB_USE_STAGE
 #define NB_USE_STAGE 1
 #endif
 constexpr bool kUseStage = NB_USE_STAGE != 0;
 
-__device__ __forceinline__ int stage_granule(int r, int p) { return r * 8 + (p ^ ((r >> 1) & 7)); }
+__device__ __forceinline__ int stage_granule(int r, int p) {
+  return kStageNG == 8 ? r * 8 + (p ^ ((r >> 1) & 7)) : r * kStageNG + (p ^ (r & 15));
+}
 
 // Destination of outputs the caller did not request (and of the lanes that
 // hold no label): the fast path stores unconditionally so that the number of
@@ -423,41 +437,42 @@ __global__ __launch_bounds__(kStageThreads) void scoreM_stage_kernel(ScoreMArgs 
   const int64_t nwaves = (int64_t)gridDim.x * kStageWaves;
   const int ngroups = (a.F + kStageGB - 1) / kStageGB;
   const float bias = (col < a.ns) ? a.row_bias[col] : 0.0f;
-  // load lane layout: instruction j covers files 8j + (lane >> 3), granule lane & 7
-  const int lr = lane >> 3, lp = lane & 7;
-  uint32_t rel[4];
+  // load lane layout: instruction j covers files kStageFPI j + lane / kStageNG,
+  // granule lane % kStageNG
+  const int lr = lane / kStageNG, lp = lane % kStageNG;
+  uint32_t rel[kStageLoads];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) rel[j] = (uint32_t)((8 * j + lr) * ld) + 16 * lp;
-  int wpos[4];
+  for (int j = 0; j < kStageLoads; ++j) rel[j] = (uint32_t)((kStageFPI * j + lr) * ld) + 16 * lp;
+  int wpos[kStageLoads];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) wpos[j] = stage_granule(8 * j + lr, lp);
+  for (int j = 0; j < kStageLoads; ++j) wpos[j] = stage_granule(kStageFPI * j + lr, lp);
   // operand lane layout: tile mt, window u -> file 16 mt + col, granule 4 u + q
-  int rpos[2][2];
+  int rpos[kStageMT][kStageWin];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < kStageMT; ++mt)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) rpos[mt][u] = stage_granule(16 * mt + col, 4 * u + q);
+    for (int u = 0; u < kStageWin; ++u) rpos[mt][u] = stage_granule(16 * mt + col, 4 * u + q);
 
-  f32x4 acc[2][1];
+  f32x4 acc[kStageMT][1];
   auto zero_acc = [&]() {
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) acc[mt][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int mt = 0; mt < kStageMT; ++mt) acc[mt][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   };
   // transpose one group through the stage and multiply it into acc
-  auto compute_group = [&](int g, const dev::u32x4 (&src)[4]) {
+  auto compute_group = [&](int g, const dev::u32x4 (&src)[kStageLoads]) {
     // the previous group's operand reads are done before the stage is
     // rewritten: LDS operations of a wave complete in order
 #pragma unroll
-    for (int j = 0; j < 4; ++j) stg[wpos[j]] = src[j];
+    for (int j = 0; j < kStageLoads; ++j) stg[wpos[j]] = src[j];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < kStageWin; ++u) {
       const int f0 = g * kStageGB + u * kWindow;         // first feature of the window
-      dev::u32x4 av[2][2];
+      dev::u32x4 av[kStageMT][2];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
+      for (int mt = 0; mt < kStageMT; ++mt) {
         dev::u32x4 xv = stg[rpos[mt][u]];
         if (XT == NB_X_FP8 && f0 + 16 * q + 16 > a.F) {   // NaN encodings past the last feature
           const int nv = max(0, a.F - (f0 + 16 * q));
@@ -473,7 +488,7 @@ __global__ __launch_bounds__(kStageThreads) void scoreM_stage_kernel(ScoreMArgs 
       const dev::u32x4 b0 = tbl[col * gpr + (G ^ col)];
       const dev::u32x4 b1 = tbl[col * gpr + ((G + 1) ^ col)];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
+      for (int mt = 0; mt < kStageMT; ++mt) {
         acc[mt][0] = mfma(av[mt][0], b0, acc[mt][0]);
         acc[mt][0] = mfma(av[mt][1], b1, acc[mt][0]);
       }
@@ -484,7 +499,7 @@ __global__ __launch_bounds__(kStageThreads) void scoreM_stage_kernel(ScoreMArgs 
   const bool want_lab = a.labels != nullptr, want_lp = a.log_post != nullptr;
   auto finish_fast = [&](int64_t row0) {
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+    for (int mt = 0; mt < kStageMT; ++mt) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t row = row0 + 16 * mt + 4 * q + i;
@@ -517,17 +532,17 @@ __global__ __launch_bounds__(kStageThreads) void scoreM_stage_kernel(ScoreMArgs 
   // The prefetch past the last unit re-reads the last unit (an L2 hit).
   const int my_tiles = (a.nfast > wave_id) ? (int)((a.nfast - wave_id + nwaves - 1) / nwaves) : 0;
   const int units = my_tiles * ngroups;
-  auto issue = [&](int k, dev::u32x4 (&dst)[4]) {
+  auto issue = [&](int k, dev::u32x4 (&dst)[kStageLoads]) {
     k = min(k, units - 1);
     const int it = k / ngroups, g = k - it * ngroups;
     const int64_t wbase = (wave_id + (int64_t)it * nwaves) * kStageFiles * ld + (int64_t)g * kStageGB;
     const auto rsrc = dev::make_rsrc(a.x + wbase, a.total_bytes - wbase);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) dst[j] = dev::buffer_load16(rsrc, rel[j]);
+    for (int j = 0; j < kStageLoads; ++j) dst[j] = dev::buffer_load16(rsrc, rel[j]);
     __builtin_amdgcn_sched_barrier(0);
   };
   int cg = 0, ct = 0;
-  auto consume = [&](const dev::u32x4 (&src)[4]) {
+  auto consume = [&](const dev::u32x4 (&src)[kStageLoads]) {
     compute_group(cg, src);
     if (++cg == ngroups) {
       finish_fast((wave_id + (int64_t)ct * nwaves) * kStageFiles);
@@ -538,20 +553,21 @@ __global__ __launch_bounds__(kStageThreads) void scoreM_stage_kernel(ScoreMArgs 
   };
   zero_acc();
   if (units > 0) {
-    static_assert(kStageDepth == 3, "the unit loop below is written for three register buffers");
-    dev::u32x4 b0[4], b1[4], b2[4];
-    issue(0, b0);
-    issue(1, b1);
-    for (int k = 0;; k += 3) {
-      issue(k + 2, b2);
-      consume(b0);
-      if (k + 1 >= units) break;
-      issue(k + 3, b0);
-      consume(b1);
-      if (k + 2 >= units) break;
-      issue(k + 4, b1);
-      consume(b2);
-      if (k + 3 >= units) break;
+    // kStageDepth register buffers in rotation: unit k + kStageDepth - 1 is
+    // issued just before unit k is consumed
+    dev::u32x4 buf[kStageDepth][kStageLoads];
+#pragma unroll
+    for (int d = 0; d < kStageDepth - 1; ++d) issue(d, buf[d]);
+    bool done = false;
+    for (int k = 0; !done; k += kStageDepth) {
+#pragma unroll
+      for (int d = 0; d < kStageDepth; ++d) {
+        if (!done) {
+          issue(k + d + kStageDepth - 1, buf[(d + kStageDepth - 1) % kStageDepth]);
+          consume(buf[d]);
+          if (k + d + 1 >= units) done = true;
+        }
+      }
     }
   }
 
@@ -561,17 +577,17 @@ __global__ __launch_bounds__(kStageThreads) void scoreM_stage_kernel(ScoreMArgs 
     const int64_t row0 = wt * kStageFiles;
     zero_acc();
     for (int g = 0; g < ngroups; ++g) {
-      dev::u32x4 v[4];
+      dev::u32x4 v[kStageLoads];
       const int64_t wbase = row0 * ld + (int64_t)g * kStageGB;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kStageLoads; ++j) {
         v[j] = dev::u32x4{0u, 0u, 0u, 0u};
         const int64_t off = wbase + rel[j];
-        if (row0 + 8 * j + lr < a.n) v[j] = dev::load16_guarded(a.x + off, a.total_bytes - off);
+        if (row0 + kStageFPI * j + lr < a.n) v[j] = dev::load16_guarded(a.x + off, a.total_bytes - off);
       }
       compute_group(g, v);
     }
-    epilogue<1, 2>(a, acc, lane, row0);
+    epilogue<1, kStageMT>(a, acc, lane, row0);
   }
 }
 

@@ -167,7 +167,7 @@ def test_more_classes_than_vector_path_rejected():
 
 
 # Sixteen classes with labels and log posteriors only take the staged
-# matrix-core kernel (whole-line loads transposed through LDS).
+# matrix-core kernel (512-byte runs of each file transposed through LDS).
 STAGED = [(4096, 3000), (1000, 1), (1000, 31), (1000, 33), (129 * 4, 777), (4, 100), (4000, 257), (2048, 4097)]
 
 

@@ -800,8 +800,14 @@ def compact(leg: str, res: dict) -> dict:
         for k in ("speedup_bf16_u8_vs_fp32", "speedup_bf16_fp8_vs_fp32", "bf16_vs_fp32_labels_identical_all_files",
                   "fp8_vs_fp32_labels_identical_all_files"):
             out[k] = r3(res[k])
-        if res.get("error_vs_oracle"):
-            out["error_vs_oracle"] = res["error_vs_oracle"]
+        e = res.get("error_vs_oracle")
+        if e:
+            ps = e["paths"]
+            out["error_vs_oracle"] = {
+                "source": "profiles/precision_errors.json",
+                "paths": len(ps),
+                "label_agreement_above_band_min": min(p.get("label_agreement_above_band", 1.0) for p in ps),
+                "post_max_abs_err_max": max(p.get("post_max_abs_err", 0.0) for p in ps)}
         return out
     if leg == "groups":
         out = {k: res[k] for k in ("n_files",)}

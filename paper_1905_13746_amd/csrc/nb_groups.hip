@@ -457,8 +457,10 @@ __global__ __launch_bounds__(kThreads) void score2_groups_sweep_kernel(GroupsArg
       nx.rb[1] = d.rb[1];
     };
     dev::u32x4 fb[FL];
-    auto launch = [&](const Next& nx) {
-      const uint32_t span = nx.lead + (uint32_t)((nx.nrows - 1) * nx.ld + F);
+    // live == false: the same instructions with every offset out of range
+    // (no memory access), for the iteration that has no next block
+    auto launch = [&](const Next& nx, bool live) {
+      const uint32_t span = live ? nx.lead + (uint32_t)((nx.nrows - 1) * nx.ld + F) : 0u;
       // the window lies in bounds (the host stages only buffers holding a window)
       const auto rsrc = dev::make_rsrc(dev::uniform_ptr(nx.base), (int64_t)FL * 1024);
 #pragma unroll
@@ -484,15 +486,20 @@ __global__ __launch_bounds__(kThreads) void score2_groups_sweep_kernel(GroupsArg
 
     Next cur, nxt;
     prep(0, cur);
-    launch(cur);
+    launch(cur, true);
     load_table_regs(cur.table);
     if (nb > 1) prep(1, nxt);
     for (int k = 0; k < nb; ++k) {
       // the launched block lands in LDS; the next one goes out
 #pragma unroll
       for (int q = 0; q < FL; ++q) *reinterpret_cast<dev::u32x4*>(mine + q * kPiece + 16 * lane) = fb[q];
+      // every iteration issues the window loads (the last one with no
+      // memory access), so the compiler's wait counts for the window stay
+      // exact; issued only when a next block exists, they made it wait for
+      // every outstanding load before writing the window to LDS (measured:
+      // 3-4% slower)
       const bool more = k + 1 < nb;
-      if (more) launch(nxt);
+      launch(more ? nxt : cur, more);
 
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
@@ -527,8 +534,9 @@ __global__ __launch_bounds__(kThreads) void score2_groups_sweep_kernel(GroupsArg
       for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int s2 = 0; s2 < NS; ++s2) acc[i][s2] = 0.0f;
-      // the next block's table, when its group differs (the loads land
-      // with its window)
+      // the next block's table weights, when its group differs (measured:
+      // reloading them for every block, which would keep the wait counts
+      // exact, costs 9% with FP32 tables of many groups)
       if (more && nxt.group != cur.group) load_table_regs(nxt.table);
       cur = nxt;
       if (k + 2 < nb) prep(k + 2, nxt);

@@ -121,6 +121,26 @@ __device__ __forceinline__ void accumulate_seg(const dev::u32x4 (&v)[(XT == NB_X
 // Destination of outputs the caller did not request: the fast path stores
 // every output unconditionally so the number of memory operations in flight
 // is known at compile time (loads of the next unit stay in flight).
+// Output stores through global-address-space pointers.  Outputs always live
+// in device memory; a pointer whose origin the compiler cannot see (read
+// from LDS, as the grouped sweep's descriptors are) would otherwise become a
+// flat store, which the hardware counts on both the vector-memory and the
+// LDS counters, and the compiler then waits for every outstanding load
+// before the loop's next LDS access.
+template <class T>
+__device__ __forceinline__ void store_out(T* p, const T& v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte outputs");
+  if constexpr (sizeof(T) == 4) {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, 4);
+    *(__attribute__((address_space(1))) uint32_t*)p = u;
+  } else {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    *(__attribute__((address_space(1))) uint64_t*)p = u;
+  }
+}
+
 __device__ int32_t g_sink_label[64];
 __device__ float2 g_sink_pair[64];
 
@@ -189,23 +209,23 @@ __device__ __forceinline__ void finish_block(const Score2Args& a, float (&acc)[R
       if (FAST) {
         int32_t* pl = want_lab ? a.labels + row : g_sink_label + lane;
         float2* pp = want_lp ? reinterpret_cast<float2*>(a.log_post) + row : g_sink_pair + lane;
-        *pl = delta > 0.0f ? 1 : 0;
-        *pp = lp;
+        store_out(pl, delta > 0.0f ? 1 : 0);
+        store_out(pp, lp);
         if (NS == 2) {
           float2 sc;
           sc.x = stage[wave][NS - 1][L] + rb[NS - 1];
           sc.y = sc.x + delta;
           float2* ps = want_sc ? reinterpret_cast<float2*>(a.scores) + row : g_sink_pair + lane;
-          *ps = sc;
+          store_out(ps, sc);
         }
       } else {
-        if (want_lab) a.labels[row] = delta > 0.0f ? 1 : 0;
-        if (want_lp) reinterpret_cast<float2*>(a.log_post)[row] = lp;
+        if (want_lab) store_out(a.labels + row, delta > 0.0f ? 1 : 0);
+        if (want_lp) store_out(reinterpret_cast<float2*>(a.log_post) + row, lp);
         if (NS == 2 && want_sc) {
           float2 sc;
           sc.x = stage[wave][NS - 1][L] + rb[NS - 1];
           sc.y = sc.x + delta;
-          reinterpret_cast<float2*>(a.scores)[row] = sc;
+          store_out(reinterpret_cast<float2*>(a.scores) + row, sc);
         }
       }
     }

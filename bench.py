@@ -15,8 +15,9 @@ label + 2 x 4-byte log posteriors per file) over its average launch duration,
 measured with HIP events on the launch stream.  `cpu_baseline` times the FP64
 oracle on the host (one thread, the paper's sequential program) on the same
 step's inputs.  Extra objects (skip with --no-extras):
-  f_sweep    scoring bandwidth of the two-class kernel at F = 100, 500, 5000, and
-             of the int32-feature variant at F = 1000
+  f_sweep    scoring bandwidth of the two-class kernel at F = 100, 500, 5000, of
+             the Bernoulli form at F = 1000 (with its training time), and of the
+             int32-feature variant at F = 1000
   precision  16 classes, F = 4096, 4,000,000 files: the plain FP32 vector path
              vs the BF16 table on the matrix cores (uint8 and FP8 features),
              with the labels of the paths compared on every file.
@@ -263,6 +264,26 @@ def f_sweep(nbg, W):
                        "frac_of_peak": gbs / HBM_PEAK_GBPS}
         del Xt, lab, lp
         torch.cuda.empty_cache()
+    # the Bernoulli form of the F = 1000 workload (presence x > 0): training
+    # on 200,000 files and scoring 1,000,000, as the headline step
+    F, n = 1000, 1_000_000
+    wl = W.binary_u8(F)
+    X, y = wl.train_set(200_000, device="cuda")
+    m = nbg.Model(2, F, "bernoulli")
+    ws = nbg.train_workspace(m, X.shape[0])
+    train_ms = timed(lambda: nbg.train(m, X, y, workspace=ws, asynchronous=True))
+    if nbg.model_status(m) != 0:
+        raise RuntimeError("Bernoulli training failed")
+    del X, y, ws
+    Xt = wl.test_set(n, device="cuda")[0]
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    lp = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    ms = timed(lambda: nbg.score(m, Xt, out=(lab, lp, None)))
+    gbs = n * (F + 12) / (ms / 1e3) / 1e9
+    out["1000_bernoulli"] = {"n_files": n, "ms": ms, "files_per_s": n / (ms / 1e3), "GBps": gbs,
+                             "frac_of_peak": gbs / HBM_PEAK_GBPS, "train_ms": train_ms}
+    del Xt, lab, lp
+    torch.cuda.empty_cache()
     # the int32-feature variant of the F = 1000 workload (4 bytes per feature)
     F, n = 1000, 1_000_000
     wl = W.binary_u8(F)
@@ -792,7 +813,8 @@ def compact(leg: str, res: dict) -> dict:
     timed kernel, the speed-ups and the agreement figures."""
     r3 = (lambda v: None if v is None else round(float(v), 4))
     if leg == "f_sweep":
-        return {k: {"files_per_s": round(v["files_per_s"]), "frac_of_peak": r3(v["frac_of_peak"])}
+        return {k: {"files_per_s": round(v["files_per_s"]), "frac_of_peak": r3(v["frac_of_peak"]),
+                    **({"train_ms": r3(v["train_ms"])} if "train_ms" in v else {})}
                 for k, v in res.items()}
     if leg == "precision":
         out = {k: {"ms": r3(res[k]["ms"]), "frac_of_peak": r3(res[k]["frac_of_peak"])}

@@ -1283,7 +1283,7 @@ int autotune(nb_group_plan* p, hipStream_t s) {
       if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(NB_EHIP, "hipEventRecord");
       if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(NB_EHIP, "hipEventSynchronize");
       ms_r[r] = 0.0f;
-      if (!rc) hipEventElapsedTime(&ms_r[r], e0, e1);
+      if (!rc && hipEventElapsedTime(&ms_r[r], e0, e1) != hipSuccess) rc = fail(NB_EHIP, "hipEventElapsedTime");
     }
     if (rc) break;
     std::sort(ms_r, ms_r + kReps);
@@ -1293,8 +1293,9 @@ int autotune(nb_group_plan* p, hipStream_t s) {
       best_t = t;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  // releases on a path that reports its own status
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   p->w.code = best_t;
   p->tuned = 1;
@@ -1303,12 +1304,12 @@ int autotune(nb_group_plan* p, hipStream_t s) {
 
 void plan_free(nb_group_plan* p) {
   if (!p) return;
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
-  if (p->dev) hipFree(p->dev);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->dev) (void)hipFree(p->dev);
   for (int i = 0; i < 2; ++i) {
-    if (p->staged[i]) hipEventDestroy(p->staged[i]);
-    if (p->pinned[i]) hipHostFree(p->pinned[i]);
+    if (p->staged[i]) (void)hipEventDestroy(p->staged[i]);
+    if (p->pinned[i]) (void)hipHostFree(p->pinned[i]);
   }
   delete p;
 }
@@ -1364,15 +1365,15 @@ int plan_build(nb_group_plan* p, const nb_model* models, int32_t n_models, const
   hipStream_t cs;
   NB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     return fail(NB_EHIP, "hipStreamBeginCapture failed");
   }
   rc = launch_grouped(p->launch, carve(p->dev, (size_t)p->cap_groups), cs);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &graph);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (rc) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return rc;
   }
   if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");

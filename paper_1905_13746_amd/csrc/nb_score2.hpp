@@ -118,9 +118,6 @@ __device__ __forceinline__ void accumulate_seg(const dev::u32x4 (&v)[(XT == NB_X
   }
 }
 
-// Destination of outputs the caller did not request: the fast path stores
-// every output unconditionally so the number of memory operations in flight
-// is known at compile time (loads of the next unit stay in flight).
 // Output stores through global-address-space pointers.  Outputs always live
 // in device memory; a pointer whose origin the compiler cannot see (read
 // from LDS, as the grouped sweep's descriptors are) would otherwise become a
@@ -141,6 +138,9 @@ __device__ __forceinline__ void store_out(T* p, const T& v) {
   }
 }
 
+// Destination of outputs the caller did not request: the fast path stores
+// every output unconditionally so the number of memory operations in flight
+// is known at compile time (loads of the next unit stay in flight).
 __device__ int32_t g_sink_label[64];
 __device__ float2 g_sink_pair[64];
 

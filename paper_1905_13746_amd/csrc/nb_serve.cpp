@@ -186,12 +186,14 @@ class Server {
     }
     if (!rc) rc = loop();
     if (!sim_) {
+      // drain and release; a failure here is reported unless an earlier
+      // error already is
       for (auto s : streams_)
-        if (s) hipStreamSynchronize(s);
+        if (s && hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(NB_EHIP, "hipStreamSynchronize");
       for (auto e : events_)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
       for (auto s : streams_)
-        if (s) hipStreamDestroy(s);
+        if (s) (void)hipStreamDestroy(s);
     }
     if (rc) return rc;
     fill_stats(st);

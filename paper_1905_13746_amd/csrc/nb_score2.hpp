@@ -110,9 +110,11 @@ __device__ __forceinline__ void accumulate_seg(const dev::u32x4 (&v)[(XT == NB_X
   }
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    // presence: byte/int counts are integers >= 0, so min(x, 1) is 1[x > 0];
-    // FP8 values may be fractional, so compare
-    const float g = !BIN ? xf[e] : (XT == NB_X_FP8 ? (xf[e] > 0.0f ? 1.0f : 0.0f) : fminf(xf[e], 1.0f));
+    // presence: for integer counts, clamping to [0, 1] is 1[x > 0], and the
+    // clamp folds into the conversion's output modifier (no extra
+    // instruction); FP8 values may be fractional, so compare
+    const float g = !BIN ? xf[e]
+                         : (XT == NB_X_FP8 ? (xf[e] > 0.0f ? 1.0f : 0.0f) : __builtin_amdgcn_fmed3f(xf[e], 0.0f, 1.0f));
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = fmaf(g, w[s][e], acc[s]);
   }

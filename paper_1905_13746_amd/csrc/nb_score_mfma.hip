@@ -75,11 +75,18 @@ __device__ __forceinline__ void to_bf16(const dev::u32x4& v, dev::u32x4& a0, dev
       f2 = hi[0];
       f3 = hi[1];
     }
-    if (BIN) {
-      f0 = f0 > 0.0f ? 1.0f : 0.0f;
-      f1 = f1 > 0.0f ? 1.0f : 0.0f;
-      f2 = f2 > 0.0f ? 1.0f : 0.0f;
-      f3 = f3 > 0.0f ? 1.0f : 0.0f;
+    if (BIN) {   // presence: a clamp to [0, 1] for byte counts (folds into the conversion), a compare for FP8
+      if (XT == NB_X_U8) {
+        f0 = __builtin_amdgcn_fmed3f(f0, 0.0f, 1.0f);
+        f1 = __builtin_amdgcn_fmed3f(f1, 0.0f, 1.0f);
+        f2 = __builtin_amdgcn_fmed3f(f2, 0.0f, 1.0f);
+        f3 = __builtin_amdgcn_fmed3f(f3, 0.0f, 1.0f);
+      } else {
+        f0 = f0 > 0.0f ? 1.0f : 0.0f;
+        f1 = f1 > 0.0f ? 1.0f : 0.0f;
+        f2 = f2 > 0.0f ? 1.0f : 0.0f;
+        f3 = f3 > 0.0f ? 1.0f : 0.0f;
+      }
     }
     o[2 * d] = pack_bf16(f0, f1);
     o[2 * d + 1] = pack_bf16(f2, f3);

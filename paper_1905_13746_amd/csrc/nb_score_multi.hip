@@ -140,7 +140,9 @@ __global__ __launch_bounds__(kThreads) void scoreC_kernel(ScoreCArgs a) {
             const uint32_t w = mine[e >> 4][(e >> 2) & 3];
             g = ((e & 2) ? __builtin_amdgcn_cvt_pk_f32_fp8(w, true) : __builtin_amdgcn_cvt_pk_f32_fp8(w, false))[e & 1];
           }
-          if (BIN) g = (XT == NB_X_FP8) ? (g > 0.0f ? 1.0f : 0.0f) : fminf(g, 1.0f);
+          // presence: a clamp to [0, 1] for integer counts (folds into the
+          // conversion), a compare for FP8 values
+          if (BIN) g = (XT == NB_X_FP8) ? (g > 0.0f ? 1.0f : 0.0f) : __builtin_amdgcn_fmed3f(g, 0.0f, 1.0f);
           const float* te = tb + e * TS;
 #pragma unroll
           for (int s4 = 0; s4 < TS; s4 += 4) {

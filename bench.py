@@ -884,7 +884,7 @@ def copy_calibration():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
               "the path shards by files with no exchange, so N GPUs would each run this step "
               "on their share.", file=sys.stderr)
         sys.exit(2)

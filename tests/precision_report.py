@@ -23,7 +23,7 @@ error), and the quantisation alone is stated as the oracle on q(x) against
 the oracle on x.
 
 Test infrastructure: only the test suite may call the oracle.  Usage (GPU):
-    python -m tests.precision_report --out gpurun_out/precision_errors
+    python -m tests.precision_report [--out profiles/precision_errors]
 writes <out>.json and <out>.md.  --quick runs a tenth of the files.
 """
 from __future__ import annotations
@@ -268,7 +268,7 @@ def markdown(res, cmd):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="gpurun_out/precision_errors")
+    ap.add_argument("--out", default="profiles/precision_errors")
     ap.add_argument("--quick", action="store_true")
     args = ap.parse_args()
     k = 10 if args.quick else 1

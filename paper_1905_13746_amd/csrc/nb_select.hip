@@ -248,11 +248,14 @@ __global__ __launch_bounds__(kGatherThreads) void gather_global_kernel(GatherArg
 // unconditionally (absent lanes and rows use out-of-range buffer offsets or
 // empty buffer ranges, which access nothing), so the number of operations
 // in flight is known at compile time and waiting for one unit's loads does
-// not wait for the units behind it.
+// not wait for the units behind it.  The one exception is a uniform one:
+// the single-element stores of a row's last partial group of outputs,
+// issued only when k is not a multiple of 4.
 
 // The four outputs j0 .. j0+3 of one lane for the row staged at `row`:
 // one packed store where all four are present, three single-element stores
-// for the row's last partial group (absent elements go out of range).
+// for the row's last partial group when k is not a multiple of 4 (absent
+// elements go out of range).
 template <int ES>
 __device__ __forceinline__ void emit4(__amdgpu_buffer_rsrc_t orsrc, const uint8_t* row, const int32_t (&o)[4],
                                       int j0, int k) {
@@ -272,11 +275,16 @@ __device__ __forceinline__ void emit4(__amdgpu_buffer_rsrc_t orsrc, const uint8_
     const dev::u32x4 q = {v[0], v[1], v[2], v[3]};
     __builtin_amdgcn_raw_buffer_store_b128(q, orsrc, (int)vo, 0, NB_STREAM_CPOL);
   }
+  // a last group of one to three outputs exists only when k is not a
+  // multiple of 4 (k is the same for every lane: a uniform branch); the
+  // paper's k values are all multiples of 4
+  if (k & 3) {
 #pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const uint32_t to = (!full && j0 + e < k) ? (uint32_t)((j0 + e) * ES) : kOutOfRange;
-    if (ES == 1) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v[e], orsrc, (int)to, 0, NB_STREAM_CPOL);
-    else __builtin_amdgcn_raw_buffer_store_b32(v[e], orsrc, (int)to, 0, NB_STREAM_CPOL);
+    for (int e = 0; e < 3; ++e) {
+      const uint32_t to = (!full && j0 + e < k) ? (uint32_t)((j0 + e) * ES) : kOutOfRange;
+      if (ES == 1) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v[e], orsrc, (int)to, 0, NB_STREAM_CPOL);
+      else __builtin_amdgcn_raw_buffer_store_b32(v[e], orsrc, (int)to, 0, NB_STREAM_CPOL);
+    }
   }
 }
 

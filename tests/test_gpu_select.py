@@ -259,6 +259,9 @@ GATHER_CASES = [
     (torch.uint8, 257, 1001, 1001, 257, "random"),       # odd stride: not dword aligned
     (torch.uint8, 5, 7, 7, 3, "random"),                 # tiny, ragged tails everywhere
     (torch.uint8, 1, 1, 1, 1, "sorted"),
+    (torch.uint8, 1003, 1000, 1000, 202, "random"),      # staged, last group of two outputs
+    (torch.uint8, 97, 2000, 2000, 21, "sorted"),         # staged, last group of one output
+    (torch.int32, 99, 300, 300, 7, "random"),            # staged int32, last group of three
     (torch.int32, 1000, 500, 500, 100, "sorted"),        # 2 KB rows
     (torch.int32, 333, 2048, 2050, 1500, "random"),      # 8 KB rows
     (torch.int32, 100, 2100, 2100, 2100, "repeats"),     # above 8 KB: global gather

@@ -16,7 +16,9 @@
 //                 of ONE class inside its slot of rows and ONE 1024-feature
 //                 chunk.  Labels are read 64 at a time and compacted with a
 //                 wave ballot, so a row is loaded only by the workgroup of its
-//                 class.  Byte counts accumulate in packed 16-bit register
+//                 class; with three or more classes a wave first collects the
+//                 matching rows of several 64-row windows in a list in LDS,
+//                 so that its row loads still go out in full batches.  Byte counts accumulate in packed 16-bit register
 //                 lanes (two features per 32-bit add), flushed to 32-bit every
 //                 <= 256 rows; four waves then combine in LDS and write one
 //                 int64 partial per (slot, class, feature) to the workspace.
@@ -65,7 +67,14 @@ struct CountArgs {
 // moment): 32-bit per-feature lane sums for byte features (flushed to int64
 // before they can wrap), int64 for int32 features (values of 65536 or more
 // are flagged: their squares could overflow the exact int64 sums).
-template <int XT, bool BIN, bool SQ = false>
+//
+// WIN: 64-row label windows whose matching rows are loaded together.  With
+// WIN = 1 the rows of a batch come straight from the window's ballot mask;
+// with more windows (many classes: a 64-row window holds about 64 / C rows of
+// one class) each wave writes the relative indices of its matching rows to a
+// list in LDS and loads them kBatch at a time, so a batch is short only at the
+// end of a list instead of in every window.
+template <int XT, bool BIN, bool SQ = false, int WIN = 1>
 __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   constexpr int EB = (XT == NB_X_I32) ? 4 : 1;   // bytes per feature
   constexpr int NV = EB;                          // 16-byte vectors per lane per row
@@ -119,29 +128,68 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
     packed_rows = 0;
   };
 
-  for (int64_t base = w_begin; base < w_end; base += 64) {
-    const int64_t r = base + lane;
-    const int lab = (r < w_end) ? a.y[r] : -1;
-    // the whole 64-row window (its chunk) lies inside the buffer
+  // the combine buffer of the four waves (after the row loop) and the
+  // per-wave row lists (inside it) share one LDS allocation
+  constexpr int kListRows = 64 * WIN;
+  static_assert(kWaves * kListRows * 4 <= (kWaves - 1) * kSeg * 64 * 8, "row lists exceed the shared buffer");
+  __shared__ __align__(16) int64_t red[kWaves - 1][kSeg][64];
+  uint32_t* const lst = reinterpret_cast<uint32_t*>(&red[0][0][0]) + wave * kListRows;
+
+  for (int64_t base = w_begin; base < w_end; base += kListRows) {
+    uint64_t mask = 0;   // WIN == 1: the window's matching rows
+    int total = 0;       // WIN > 1: rows in this wave's list
+#pragma unroll
+    for (int j = 0; j < WIN; ++j) {
+      const int64_t r = base + 64 * j + lane;
+      const int lab = (r < w_end) ? a.y[r] : -1;
+      if (r < w_end && (lab < 0 || lab >= a.C)) bad_label = true;
+      const uint64_t m = __ballot(lab == cls);
+      matched += __popcll(m);
+      if (WIN == 1) {
+        mask = m;
+      } else {
+        const int pos = total + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (lab == cls) lst[pos] = (uint32_t)(64 * j + lane);
+        total += __popcll(m);
+      }
+    }
+    // the list is written and read by the same wave, in order
+    if (WIN > 1) __builtin_amdgcn_wave_barrier();
+    // every row of the windows (their chunk) lies inside the buffer
+    const int64_t last = min(base + kListRows, w_end) - 1;
     const bool window_fast =
-        (base + 63) * a.ld_bytes + chunk_end <= a.total_bytes && 64 * a.ld_bytes < ((int64_t)1 << 31);
+        last * a.ld_bytes + chunk_end <= a.total_bytes && kListRows * a.ld_bytes < ((int64_t)1 << 31);
     const auto wrsrc = dev::make_rsrc(a.x + base * a.ld_bytes, a.total_bytes - base * a.ld_bytes);
-    if (r < w_end && (lab < 0 || lab >= a.C)) bad_label = true;
-    uint64_t mask = __ballot(lab == cls);
-    matched += __popcll(mask);
-    while (mask) {
+    for (int b = 0; WIN == 1 ? mask != 0 : b < total; b += kBatch) {
       int64_t rows[kBatch];
       int cnt = 0;
+      if (WIN == 1) {
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
-        if (mask) {
-          const int idx = __ffsll((unsigned long long)mask) - 1;
-          mask &= mask - 1;
-          rows[k] = base + idx;
-          ++cnt;
-        } else {
-          rows[k] = -1;
+        for (int k = 0; k < kBatch; ++k) {
+          if (mask) {
+            const int idx = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            rows[k] = base + idx;
+            ++cnt;
+          } else {
+            rows[k] = -1;
+          }
         }
+      } else {
+        // b is a multiple of kBatch: four aligned 16-byte reads per 16 rows
+        cnt = min(kBatch, total - b);
+        uint32_t rel[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; k += 4) {
+          const uint4 q4 = *reinterpret_cast<const uint4*>(lst + b + k);
+          rel[k] = q4.x;
+          rel[k + 1] = q4.y;
+          rel[k + 2] = q4.z;
+          rel[k + 3] = q4.w;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) rows[k] = (k < cnt) ? base + rel[k] : -1;
       }
       dev::u32x4 v[kBatch][NV];
       if (window_fast) {
@@ -225,6 +273,8 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
         if (packed_rows > (SQ ? 65536 : 256) - kBatch) flush();
       }
     }
+    // this list's reads are done before the next windows overwrite it
+    if (WIN > 1) __builtin_amdgcn_wave_barrier();
   }
   if (XT != NB_X_I32) flush();
 
@@ -237,8 +287,9 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
           (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0) | (any_big ? kFlagOverflow : 0);
   }
 
-  // combine the four waves in LDS, then one partial row per workgroup
-  __shared__ int64_t red[kWaves - 1][kSeg][64];
+  // combine the four waves in LDS, then one partial row per workgroup (the
+  // buffer held the row lists: the flag reductions above are workgroup
+  // barriers, so every wave is past its loop)
   __shared__ int64_t red_m[kWaves];
   if (wave > 0) {
 #pragma unroll
@@ -615,11 +666,31 @@ __global__ __launch_bounds__(256) void gauss_rows(const double* __restrict__ mea
   }
 }
 
+// 64-row label windows per row list: about 32 matching rows per list (two
+// full batches) for 2, 3 to 7, and 8 or more classes.
+int count_win(int32_t C) { return C <= 2 ? 1 : (C <= 7 ? 4 : 8); }
+
+template <int XT, bool BIN, bool SQ>
+const void* count_fn_win(int win) {
+  switch (win) {
+    case 1: return reinterpret_cast<const void*>(count_kernel<XT, BIN, SQ, 1>);
+    case 4: return reinterpret_cast<const void*>(count_kernel<XT, BIN, SQ, 4>);
+    default: return reinterpret_cast<const void*>(count_kernel<XT, BIN, SQ, 8>);
+  }
+}
+
+// The count kernel for a feature type, kind and pass (SQ: square sums).
+const void* count_fn(int32_t xtype, bool bin, bool sq, int win) {
+  if (xtype == NB_X_I32)
+    return sq ? count_fn_win<NB_X_I32, false, true>(win)
+              : (bin ? count_fn_win<NB_X_I32, true, false>(win) : count_fn_win<NB_X_I32, false, false>(win));
+  return sq ? count_fn_win<NB_X_U8, false, true>(win)
+            : (bin ? count_fn_win<NB_X_U8, true, false>(win) : count_fn_win<NB_X_U8, false, false>(win));
+}
+
 // Workgroups of the count kernel resident on the device at once.
-int count_capacity(int32_t xtype) {
-  const void* fn = (xtype == NB_X_I32) ? reinterpret_cast<const void*>(count_kernel<NB_X_I32, false>)
-                                       : reinterpret_cast<const void*>(count_kernel<NB_X_U8, false>);
-  return resident_per_cu(fn, kThreads, 0) * device_cu_count();
+int count_capacity(int32_t xtype, int win) {
+  return resident_per_cu(count_fn(xtype, false, false, win), kThreads, 0) * device_cu_count();
 }
 
 // Row slots of the count pass: as many (slot, class, chunk) workgroups as
@@ -627,7 +698,7 @@ int count_capacity(int32_t xtype) {
 // empty round), with at least kMinRowsPerSlot rows per slot.
 int64_t train_slots(int32_t C, int32_t F, int64_t n, int32_t xtype) {
   const int64_t nch = (align_up((size_t)F, kFeaturePad)) / kChunk;
-  const int64_t units = std::max<int64_t>(1, count_capacity(xtype));
+  const int64_t units = std::max<int64_t>(1, count_capacity(xtype, count_win(C)));
   const int64_t s = std::max<int64_t>(1, units / (C * nch));
   const int64_t by_rows = std::max<int64_t>(1, (n + kMinRowsPerSlot - 1) / kMinRowsPerSlot);
   return std::max<int64_t>(1, std::min(s, by_rows));
@@ -857,21 +928,17 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   ca.Fp = Fp;
   const dim3 grid((unsigned)S, (unsigned)C, (unsigned)(Fp / kChunk));
   const bool bin = (m->kind == NB_BERNOULLI);
-  if (xtype == NB_X_U8) {
-    if (bin) hipLaunchKernelGGL((count_kernel<NB_X_U8, true>), grid, dim3(kThreads), 0, s, ca);
-    else hipLaunchKernelGGL((count_kernel<NB_X_U8, false>), grid, dim3(kThreads), 0, s, ca);
-  } else {
-    if (bin) hipLaunchKernelGGL((count_kernel<NB_X_I32, true>), grid, dim3(kThreads), 0, s, ca);
-    else hipLaunchKernelGGL((count_kernel<NB_X_I32, false>), grid, dim3(kThreads), 0, s, ca);
+  const int win = count_win(C);
+  {
+    void* args[] = {&ca};
+    NB_HIP_CHECK(hipLaunchKernel(count_fn(xtype, bin, false, win), grid, dim3(kThreads), args, 0, s));
   }
-  NB_HIP_CHECK(hipGetLastError());
   if (gauss) {   // second pass: the sums of squares
     CountArgs cq = ca;
     cq.part = part_sq;
     cq.flag_part = flag_part + n_flags1;
-    if (xtype == NB_X_U8) hipLaunchKernelGGL((count_kernel<NB_X_U8, false, true>), grid, dim3(kThreads), 0, s, cq);
-    else hipLaunchKernelGGL((count_kernel<NB_X_I32, false, true>), grid, dim3(kThreads), 0, s, cq);
-    NB_HIP_CHECK(hipGetLastError());
+    void* args[] = {&cq};
+    NB_HIP_CHECK(hipLaunchKernel(count_fn(xtype, false, true, win), grid, dim3(kThreads), args, 0, s));
   }
 
   const dim3 rgrid((unsigned)((F + 63) / 64), (unsigned)C, (unsigned)tw.RS);

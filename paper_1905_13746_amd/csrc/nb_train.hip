@@ -666,15 +666,17 @@ __global__ __launch_bounds__(256) void gauss_rows(const double* __restrict__ mea
   }
 }
 
-// 64-row label windows per row list: about 32 matching rows per list (two
-// full batches) for 2, 3 to 7, and 8 or more classes.
-int count_win(int32_t C) { return C <= 2 ? 1 : (C <= 7 ? 4 : 8); }
+// 64-row label windows per row list: at least about 32 matching rows per
+// list (two full batches) for 2, 3 to 7 and 8 to 11 classes, about 64 from 12
+// classes on.
+int count_win(int32_t C) { return C <= 2 ? 1 : (C <= 7 ? 4 : (C <= 11 ? 8 : 16)); }
 
 template <int XT, bool BIN, bool SQ>
 const void* count_fn_win(int win) {
   switch (win) {
     case 1: return reinterpret_cast<const void*>(count_kernel<XT, BIN, SQ, 1>);
     case 4: return reinterpret_cast<const void*>(count_kernel<XT, BIN, SQ, 4>);
+    case 16: return reinterpret_cast<const void*>(count_kernel<XT, BIN, SQ, 16>);
     default: return reinterpret_cast<const void*>(count_kernel<XT, BIN, SQ, 8>);
   }
 }
@@ -693,13 +695,19 @@ int count_capacity(int32_t xtype, int win) {
   return resident_per_cu(count_fn(xtype, false, false, win), kThreads, 0) * device_cu_count();
 }
 
-// Row slots of the count pass: as many (slot, class, chunk) workgroups as
-// fit on the device in one round (a few more would run as a second, nearly
-// empty round), with at least kMinRowsPerSlot rows per slot.
+// Row slots of the count pass, with at least kMinRowsPerSlot rows per slot.
+// Two classes: as many (slot, class, chunk) workgroups as fit on the device
+// in one round (a few more would run as a second, nearly empty round).  With
+// more classes a workgroup's work is the rows of its class in its slot, which
+// differs between classes as much as their priors do; four rounds of smaller
+// slots let the workgroups of the small classes finish and make room, so that
+// the large classes' rows are spread over the whole device.
+constexpr int64_t kManyClassRounds = 4;
 int64_t train_slots(int32_t C, int32_t F, int64_t n, int32_t xtype) {
   const int64_t nch = (align_up((size_t)F, kFeaturePad)) / kChunk;
   const int64_t units = std::max<int64_t>(1, count_capacity(xtype, count_win(C)));
-  const int64_t s = std::max<int64_t>(1, units / (C * nch));
+  const int64_t rounds = C > 2 ? kManyClassRounds : 1;
+  const int64_t s = std::max<int64_t>(1, rounds * units / (C * nch));
   const int64_t by_rows = std::max<int64_t>(1, (n + kMinRowsPerSlot - 1) / kMinRowsPerSlot);
   return std::max<int64_t>(1, std::min(s, by_rows));
 }

@@ -387,11 +387,19 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
   const int t = threadIdx.x;
   int32_t* T = a.counts + (int64_t)c * a.F;
 
+  // the count kernel's flags (every class workgroup gathers all of them),
+  // loaded first: they do not depend on the sums below
+  int32_t fl = 0;
+  for (int i = t; i < a.n_flags; i += 256) fl |= a.flag_part[i];
+
   // Every partial is loaded before any is summed (the loads are independent;
-  // summed one at a time they would form a chain of L2 round trips).
+  // summed one at a time they would form a chain of L2 round trips).  With
+  // F <= 1024 a thread's counts stay in registers for the tables below.
   constexpr int kFeatPerPass = 4;
+  const bool one_pass = a.F <= 256 * kFeatPerPass;
   int64_t s = 0;
   bool over = false;
+  int32_t kept[kFeatPerPass];
   for (int f0 = t; f0 < a.F; f0 += 256 * kFeatPerPass) {
     int64_t v[kFeatPerPass][kReduceSplit];
 #pragma unroll
@@ -407,23 +415,17 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
       int64_t tot = 0;
 #pragma unroll
       for (int r = 0; r < kReduceSplit; ++r) tot += v[q][r];
+      if (tot > INT32_MAX) {
+        over = true;
+        tot = INT32_MAX;
+      }
+      kept[q] = (int32_t)tot;
       if (f < a.F) {
-        if (tot > INT32_MAX) {
-          over = true;
-          tot = INT32_MAX;
-        }
         T[f] = (int32_t)tot;
         s += tot;
       }
     }
   }
-  // the count kernel's flags (every class workgroup gathers all of them)
-  int32_t fl = 0;
-  for (int i = t; i < a.n_flags; i += 256) fl |= a.flag_part[i];
-  const int any_over = __syncthreads_or(over || (fl & kFlagOverflow));
-  const int any_bad = __syncthreads_or(fl & kFlagBadLabel);
-  const int any_neg = __syncthreads_or(fl & kFlagNegative);
-  const int any_idx = __syncthreads_or(fl & kFlagBadIndex);
   // class totals: one partial per thread, summed in a fixed order
   __shared__ int64_t snc[kMaxClasses];
   if (t < a.C) {
@@ -435,42 +437,60 @@ __global__ __launch_bounds__(256) void class_tables(TableArgs a) {
     for (int r = 0; r < kReduceSplit; ++r) tot += w[r];
     snc[t] = tot;
   }
+  // S_c (wave sums, then the four wave totals in a fixed order) and the OR
+  // of every thread's flags, behind one barrier
+  int bits = (over ? kFlagOverflow : 0) | (fl & (kFlagOverflow | kFlagBadLabel | kFlagNegative | kFlagBadIndex));
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    s += __shfl_xor(s, m);
+    bits |= __shfl_xor(bits, m);
+  }
   __shared__ int64_t red_i[4];
-  const int64_t Sc = block_sum<int64_t>(s, red_i);
+  __shared__ int red_b[4];
+  if ((t & 63) == 0) {
+    red_i[t >> 6] = s;
+    red_b[t >> 6] = bits;
+  }
+  __syncthreads();
+  const int64_t Sc = red_i[0] + red_i[1] + red_i[2] + red_i[3];
+  bits = red_b[0] | red_b[1] | red_b[2] | red_b[3];
   int64_t N = 0;
   for (int k = 0; k < a.C; ++k) N += snc[k];
   const int64_t Nc = snc[c];
   if (t == 0) {
     a.class_totals[c] = Nc;
     a.class_sums[c] = (a.kind == NB_BERNOULLI) ? Nc : Sc;
-    a.class_flags[c] = (any_over ? kFlagOverflow : 0) | ((Nc < a.min_files || Nc < 1) ? kFlagMinFiles : 0) |
-                       (any_bad ? kFlagBadLabel : 0) | (any_neg ? kFlagNegative : 0) |
-                       (any_idx ? kFlagBadIndex : 0);
+    a.class_flags[c] = bits | ((Nc < a.min_files || Nc < 1) ? kFlagMinFiles : 0);
   }
 
   if (a.kind == NB_GAUSSIAN) return;   // its tables follow from the moments (gauss_tables)
   const double al = a.alpha;
   double part = 0.0;
-  if (a.kind == NB_MULTINOMIAL) {
-    const double den = log((double)Sc + al * (double)a.F);
-    for (int f = t; f < a.F; f += 256) {
-      const double lt = log((double)T[f] + al) - den;
-      const int64_t i = (int64_t)c * a.F + f;
-      a.log_theta[i] = lt;
+  const bool multi = (a.kind == NB_MULTINOMIAL);
+  const double den = multi ? log((double)Sc + al * (double)a.F) : log((double)Nc + 2.0 * al);
+  // feature f's tables from its count; Bernoulli terms log(1 - theta) are
+  // added to `part` in increasing f, as the one-pass and the reloading
+  // forms both visit a thread's features
+  auto emit = [&](int f, int32_t Tf) {
+    const double lt = log((double)Tf + al) - den;
+    const int64_t i = (int64_t)c * a.F + f;
+    a.log_theta[i] = lt;
+    if (multi) {
       a.log_1m_theta[i] = 0.0;
       a.weight[i] = lt;
-    }
-  } else {
-    const double den = log((double)Nc + 2.0 * al);
-    for (int f = t; f < a.F; f += 256) {
-      const double lt = log((double)T[f] + al) - den;
-      const double l1 = log((double)(Nc - T[f]) + al) - den;
-      const int64_t i = (int64_t)c * a.F + f;
-      a.log_theta[i] = lt;
+    } else {
+      const double l1 = log((double)(Nc - Tf) + al) - den;
       a.log_1m_theta[i] = l1;
       a.weight[i] = lt - l1;
       part += l1;
     }
+  };
+  if (one_pass) {
+#pragma unroll
+    for (int q = 0; q < kFeatPerPass; ++q)
+      if (t + q * 256 < a.F) emit(t + q * 256, kept[q]);
+  } else {
+    for (int f = t; f < a.F; f += 256) emit(f, T[f]);
   }
   __shared__ double red_d[4];
   const double sum_l1 = block_sum<double>(part, red_d);

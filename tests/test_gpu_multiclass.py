@@ -253,3 +253,33 @@ def test_full_size_16_classes_sampled():
     # band allows a difference at all: report the agreement, require it above 99.9%
     agree = (labels["bf16_u8"] == labels["fp32"]).float().mean().item()
     assert agree > 0.999, agree
+
+
+# The count pass of three or more classes: each wave lists its class's rows
+# of 4 (3 to 7 classes), 8 (8 to 11) or 16 (12 and more) 64-row label
+# windows and loads them 16 at a time, over four rounds of row slots.  Counts
+# are exact integers, so every count, class total and class sum equals the
+# oracle's; row counts that are no multiple of a list, skewed priors (the
+# smallest classes get few rows, the largest several full batches per list),
+# int32 features and the squares pass of the Gaussian variant included.
+LISTS = [(3, 1000, 4099, True), (8, 700, 9001, True), (11, 1036, 7777, True), (12, 64, 20011, True),
+         (9, 300, 5003, False), (16, 2000, 30001, True)]
+
+
+@pytest.mark.parametrize("kind", [nb.MULTINOMIAL, nb.BERNOULLI])
+@pytest.mark.parametrize("C,F,n,u8", LISTS, ids=[f"C{c}_F{f}_n{n}_{'u8' if u else 'i32'}" for c, f, n, u in LISTS])
+def test_training_row_lists(C, F, n, u8, kind):
+    _case(f"training row lists C={C} F={F} n={n} u8={u8} {kind}")
+    wl = family(C, F, p_zero=0.8 if u8 else 0.7, clip=u8)
+    m, om = _train(wl, n, kind)
+    assert m.trained
+    assert_tables(m, om, kind)
+
+
+@pytest.mark.parametrize("C,F,n", [(9, 300, 7001), (13, 132, 12345)])
+def test_training_row_lists_gaussian(C, F, n):
+    _case(f"training row lists gaussian C={C} F={F} n={n}")
+    wl = W.Workload(wid=9, n_classes=C, n_features=F, p_zero=0.6, clip255=True, group=C * 8192 + F,
+                    prior=np.random.default_rng(C * 1000 + F).dirichlet(np.ones(C)))
+    m, om = _train(wl, n, nb.GAUSSIAN)
+    assert_tables(m, om, nb.GAUSSIAN)

@@ -128,6 +128,17 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
     packed_rows = 0;
   };
 
+  // Cache policy of the window loads.  Two classes (WIN = 1): default, so
+  // that a cache line shared by neighbouring rows of different classes, which
+  // the two classes' workgroups load, is fetched from HBM once (their
+  // workgroups sit on the same XCD) -- 1000-byte rows share a line at every
+  // row boundary; non-temporal (nothing to share) with more classes, where
+  // default caching was slower.
+  constexpr int kCpol = (WIN == 1) ? 0 : NB_STREAM_CPOL;
+  auto load_window = [&](__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, kCpol);
+    return dev::u32x4{(uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2], (uint32_t)q[3]};
+  };
   // the combine buffer of the four waves (after the row loop) and the
   // per-wave row lists (inside it) share one LDS allocation
   constexpr int kListRows = 64 * WIN;
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
         for (int k = 0; k < kBatch; ++k) {
           const uint32_t ro = (uint32_t)((k < cnt ? rows[k] : rows[0]) - base) * (uint32_t)a.ld_bytes;
 #pragma unroll
-          for (int q = 0; q < NV; ++q) v[k][q] = dev::buffer_load16(wrsrc, ro + (uint32_t)col + 16 * q);
+          for (int q = 0; q < NV; ++q) v[k][q] = load_window(wrsrc, ro + (uint32_t)col + 16 * q);
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k)

@@ -60,7 +60,8 @@ struct CountArgs {
   int64_t* part;           // [S][C][Fp]
   int64_t* nc_part;        // [S][C]
   int32_t* flag_part;      // [S][C][chunks] error flags of each workgroup
-  int32_t F, C, Fp;
+  int64_t* zero_words;     // n_zero words cleared by workgroup (0, 0, 0), or NULL
+  int32_t F, C, Fp, n_zero;
 };
 
 // SQ: sums of squares x^2 instead of counts (the Gaussian variant's second
@@ -84,6 +85,9 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
   // from it then live in scalar registers
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
+  // the class sums reduce_counts accumulates start from zero (the kernels
+  // run in stream order)
+  if (a.zero_words && slot == 0 && cls == 0 && ch == 0 && (int)threadIdx.x < a.n_zero) a.zero_words[threadIdx.x] = 0;
   const int64_t r_begin = (int64_t)slot * a.rows_per_slot;
   const int64_t r_end = min(a.n, r_begin + a.rows_per_slot);
   // four contiguous sub-ranges, 64-row aligned
@@ -325,10 +329,12 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
 // 4 slot lanes x 64 features per workgroup; writes RS second-level partials.
 constexpr int kReduceSplit = 8;
 
+// csum (or NULL): S_c accumulated with integer atomics (exact, so the order
+// of the additions does not matter), from words the count kernel cleared.
 __global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__ part,
                                                     const int64_t* __restrict__ nc_part, int S, int C,
                                                     int F, int Fp, int64_t* __restrict__ part2,
-                                                    int64_t* __restrict__ nc2) {
+                                                    int64_t* __restrict__ nc2, int64_t* __restrict__ csum) {
   const int c = blockIdx.y, rs = blockIdx.z, RS = gridDim.z;
   const int fl = threadIdx.x & 63, sg = threadIdx.x >> 6;
   const int f = blockIdx.x * 64 + fl;
@@ -359,8 +365,15 @@ __global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__
   if (fl == 0) redm[sg] = m;
   __syncthreads();
   if (sg == 0) {
-    if (f < F) part2[((int64_t)rs * C + c) * Fp + f] = red[0][fl] + red[1][fl] + red[2][fl] + red[3][fl];
+    const int64_t tot = (f < F) ? red[0][fl] + red[1][fl] + red[2][fl] + red[3][fl] : 0;
+    if (f < F) part2[((int64_t)rs * C + c) * Fp + f] = tot;
     if (blockIdx.x == 0 && fl == 0) nc2[(int64_t)rs * C + c] = redm[0] + redm[1] + redm[2] + redm[3];
+    if (csum) {
+      int64_t w = tot;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o);
+      if (fl == 0) atomicAdd(reinterpret_cast<unsigned long long*>(csum + c), (unsigned long long)w);
+    }
   }
 }
 
@@ -566,6 +579,96 @@ __global__ __launch_bounds__(256) void form_rows(const double* __restrict__ W, c
   }
 }
 
+// Two classes, multinomial, byte features: class_tables and form_rows as one
+// launch, one thread per feature.  S_c comes from reduce_counts' exact sums,
+// and no count can exceed INT32_MAX (nb_train refuses n * 255 > INT32_MAX),
+// so a feature's tables need no other feature.  Counts, tables, bias, rows
+// and status are the same expressions, in the same FP64 operations, as in
+// class_tables followed by form_rows.  grid (Fp / 256).
+__global__ __launch_bounds__(256) void tables_rows2(TableArgs a, const int64_t* __restrict__ csum,
+                                                   float* __restrict__ rows32, uint16_t* __restrict__ rows16,
+                                                   float* __restrict__ row_bias, int32_t* __restrict__ status) {
+  const int t = threadIdx.x;
+  const int f = blockIdx.x * 256 + t;
+  const int F = a.F, Fp = a.Fp;
+  int32_t fl = 0;
+  if (blockIdx.x == 0)
+    for (int i = t; i < a.n_flags; i += 256) fl |= a.flag_part[i];
+  int64_t v[2][kReduceSplit], w[2][kReduceSplit];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < kReduceSplit; ++r) {
+      v[c][r] = (f < F && r < a.RS) ? a.part2[((int64_t)r * 2 + c) * Fp + f] : 0;
+      w[c][r] = (r < a.RS) ? a.nc2[(int64_t)r * 2 + c] : 0;
+    }
+  const int64_t Sc[2] = {csum[0], csum[1]};
+  int64_t Tc[2], Nc[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    Tc[c] = 0;
+    Nc[c] = 0;
+#pragma unroll
+    for (int r = 0; r < kReduceSplit; ++r) {
+      Tc[c] += v[c][r];
+      Nc[c] += w[c][r];
+    }
+  }
+  const double al = a.alpha;
+  if (f < F) {
+    double lt[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      a.counts[(int64_t)c * F + f] = (int32_t)Tc[c];
+      const double den = log((double)Sc[c] + al * (double)F);
+      lt[c] = log((double)Tc[c] + al) - den;
+      const int64_t i = (int64_t)c * F + f;
+      a.log_theta[i] = lt[c];
+      a.log_1m_theta[i] = 0.0;
+      a.weight[i] = lt[c];
+    }
+    const double d = lt[1] - lt[0];
+    rows32[f] = (float)d;
+    rows16[f] = dev::f64_to_bf16_rne(d);
+    rows32[(int64_t)Fp + f] = (float)lt[0];
+    rows16[(int64_t)Fp + f] = dev::f64_to_bf16_rne(lt[0]);
+  } else if (f < Fp) {
+    for (int r = 0; r <= 1; ++r) {
+      rows32[(int64_t)r * Fp + f] = 0.0f;
+      rows16[(int64_t)r * Fp + f] = 0;
+    }
+  }
+  if (blockIdx.x == 0) {
+    int bits = fl & (kFlagOverflow | kFlagBadLabel | kFlagNegative | kFlagBadIndex);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) bits |= __shfl_xor(bits, m);
+    __shared__ int red_b[4];
+    if ((t & 63) == 0) red_b[t >> 6] = bits;
+    __syncthreads();
+    if (t == 0) {
+      bits = red_b[0] | red_b[1] | red_b[2] | red_b[3];
+      const int64_t N = Nc[0] + Nc[1];
+      double bias[2];
+      int32_t flags = 0;
+      for (int c = 0; c < 2; ++c) {
+        a.class_totals[c] = Nc[c];
+        a.class_sums[c] = Sc[c];
+        bias[c] = log((double)Nc[c]) - log((double)N);
+        a.bias[c] = bias[c];
+        const int32_t cf = bits | ((Nc[c] < a.min_files || Nc[c] < 1) ? kFlagMinFiles : 0);
+        a.class_flags[c] = cf;
+        flags |= cf;
+      }
+      row_bias[0] = (float)(bias[1] - bias[0]);
+      row_bias[1] = (float)bias[0];
+      status[kStatusFlags] = flags;
+      status[kStatusTrained] = (flags == 0) ? 1 : 0;
+      status[2] = 0;
+      status[3] = 0;
+    }
+  }
+}
+
 // ------------------------------------------------------------ Gaussian
 typedef unsigned __int128 u128;
 
@@ -747,7 +850,7 @@ int64_t train_slots(int32_t C, int32_t F, int64_t n, int32_t xtype) {
 // second-level partials of each.
 struct TrainWs {
   int64_t S, RS;
-  size_t off_part, off_nc, off_part2, off_nc2, off_part_sq, off_part2_sq, off_flags, total;
+  size_t off_part, off_nc, off_part2, off_nc2, off_part_sq, off_part2_sq, off_flags, off_csum, total;
 };
 
 TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
@@ -770,6 +873,7 @@ TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
   w.off_part2_sq = take((size_t)w.RS * C * Fp * 8);
   // count-kernel flags [2][S][C][chunks] (counts, squares), then per-class flags
   w.off_flags = take(((size_t)2 * S * C * (Fp / kChunk) + C) * 4);
+  w.off_csum = take((size_t)C * 8);   // class sums of the one-launch two-class tables
   w.total = off;
   return w;
 }
@@ -824,9 +928,11 @@ SelectWs select_ws(int32_t C, int32_t k, int32_t Fp) {
 
 // Table build shared by nb_train and nb_model_select: class_tables over RS
 // second-level partials, then the scoring rows and the status word.
+// csum: the class sums from reduce_counts (two classes, multinomial, byte
+// features): the tables and rows then take one launch.
 int launch_tables(nb_model* m, const nb_layout& L, const int64_t* part2, const int64_t* nc2, int RS,
                   const int32_t* flag_part, int n_flags, int32_t* class_flags, double alpha, int min_files,
-                  hipStream_t s, const int64_t* part2_sq = nullptr) {
+                  hipStream_t s, const int64_t* part2_sq = nullptr, const int64_t* csum = nullptr) {
   uint8_t* base = static_cast<uint8_t*>(m->dev);
   TableArgs ta;
   ta.part2 = part2;
@@ -848,6 +954,14 @@ int launch_tables(nb_model* m, const nb_layout& L, const int64_t* part2, const i
   ta.RS = RS;
   ta.kind = m->kind;
   ta.min_files = min_files;
+  if (csum) {
+    hipLaunchKernelGGL(tables_rows2, dim3((unsigned)(ta.Fp / 256)), dim3(256), 0, s, ta, csum,
+                       reinterpret_cast<float*>(base + L.off_form_f32),
+                       reinterpret_cast<uint16_t*>(base + L.off_form_bf16),
+                       reinterpret_cast<float*>(base + L.off_form_bias), reinterpret_cast<int32_t*>(base + L.off_status));
+    NB_HIP_CHECK(hipGetLastError());
+    return NB_OK;
+  }
   hipLaunchKernelGGL(class_tables, dim3((unsigned)ta.C), dim3(256), 0, s, ta);
   NB_HIP_CHECK(hipGetLastError());
   if (m->kind == NB_GAUSSIAN) {
@@ -965,6 +1079,12 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   ca.F = F;
   ca.C = C;
   ca.Fp = Fp;
+  // two classes, multinomial, byte features: the class sums come from
+  // reduce_counts and the tables and rows take one launch
+  const bool fused = (C == 2 && m->kind == NB_MULTINOMIAL && xtype == NB_X_U8);
+  int64_t* csum = fused ? reinterpret_cast<int64_t*>(wsb + tw.off_csum) : nullptr;
+  ca.zero_words = csum;
+  ca.n_zero = fused ? C : 0;
   const dim3 grid((unsigned)S, (unsigned)C, (unsigned)(Fp / kChunk));
   const bool bin = (m->kind == NB_BERNOULLI);
   const int win = count_win(C);
@@ -981,15 +1101,16 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   }
 
   const dim3 rgrid((unsigned)((F + 63) / 64), (unsigned)C, (unsigned)tw.RS);
-  hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part, nc_part, (int)S, C, F, Fp, part2, nc2);
+  hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part, nc_part, (int)S, C, F, Fp, part2, nc2, csum);
   NB_HIP_CHECK(hipGetLastError());
   if (gauss) {   // (the class totals it writes again are the same values)
-    hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part_sq, nc_part, (int)S, C, F, Fp, part2_sq, nc2);
+    hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part_sq, nc_part, (int)S, C, F, Fp, part2_sq, nc2,
+                       nullptr);
     NB_HIP_CHECK(hipGetLastError());
   }
 
   rc = launch_tables(m, L, part2, nc2, (int)tw.RS, flag_part, n_flags, class_flags, alpha, min_files_per_class,
-                     s, part2_sq);
+                     s, part2_sq, csum);
   if (rc) return rc;
 
   if (flags & NB_TRAIN_ASYNC) return NB_OK;

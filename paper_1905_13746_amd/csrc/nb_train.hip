@@ -329,8 +329,10 @@ __global__ __launch_bounds__(kThreads) void count_kernel(CountArgs a) {
 // 4 slot lanes x 64 features per workgroup; writes RS second-level partials.
 constexpr int kReduceSplit = 8;
 
-// csum (or NULL): S_c accumulated with integer atomics (exact, so the order
-// of the additions does not matter), from words the count kernel cleared.
+// csum (or NULL): [RS][C] shares of S_c accumulated with integer atomics
+// (exact, so the order of the additions does not matter; one word per split
+// keeps the workgroups adding to one word few), from words the count kernel
+// cleared.
 __global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__ part,
                                                     const int64_t* __restrict__ nc_part, int S, int C,
                                                     int F, int Fp, int64_t* __restrict__ part2,
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__
       int64_t w = tot;
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o);
-      if (fl == 0) atomicAdd(reinterpret_cast<unsigned long long*>(csum + c), (unsigned long long)w);
+      if (fl == 0) atomicAdd(reinterpret_cast<unsigned long long*>(csum + (int64_t)rs * C + c), (unsigned long long)w);
     }
   }
 }
@@ -594,24 +596,26 @@ __global__ __launch_bounds__(256) void tables_rows2(TableArgs a, const int64_t* 
   int32_t fl = 0;
   if (blockIdx.x == 0)
     for (int i = t; i < a.n_flags; i += 256) fl |= a.flag_part[i];
-  int64_t v[2][kReduceSplit], w[2][kReduceSplit];
+  int64_t v[2][kReduceSplit], w[2][kReduceSplit], u[2][kReduceSplit];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int r = 0; r < kReduceSplit; ++r) {
       v[c][r] = (f < F && r < a.RS) ? a.part2[((int64_t)r * 2 + c) * Fp + f] : 0;
       w[c][r] = (r < a.RS) ? a.nc2[(int64_t)r * 2 + c] : 0;
+      u[c][r] = (r < a.RS) ? csum[(int64_t)r * 2 + c] : 0;
     }
-  const int64_t Sc[2] = {csum[0], csum[1]};
-  int64_t Tc[2], Nc[2];
+  int64_t Tc[2], Nc[2], Sc[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     Tc[c] = 0;
     Nc[c] = 0;
+    Sc[c] = 0;
 #pragma unroll
     for (int r = 0; r < kReduceSplit; ++r) {
       Tc[c] += v[c][r];
       Nc[c] += w[c][r];
+      Sc[c] += u[c][r];
     }
   }
   const double al = a.alpha;
@@ -873,7 +877,7 @@ TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
   w.off_part2_sq = take((size_t)w.RS * C * Fp * 8);
   // count-kernel flags [2][S][C][chunks] (counts, squares), then per-class flags
   w.off_flags = take(((size_t)2 * S * C * (Fp / kChunk) + C) * 4);
-  w.off_csum = take((size_t)C * 8);   // class sums of the one-launch two-class tables
+  w.off_csum = take((size_t)w.RS * C * 8);   // class-sum shares of the one-launch two-class tables
   w.total = off;
   return w;
 }
@@ -1084,7 +1088,7 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   const bool fused = (C == 2 && m->kind == NB_MULTINOMIAL && xtype == NB_X_U8);
   int64_t* csum = fused ? reinterpret_cast<int64_t*>(wsb + tw.off_csum) : nullptr;
   ca.zero_words = csum;
-  ca.n_zero = fused ? C : 0;
+  ca.n_zero = fused ? (int)(tw.RS * C) : 0;
   const dim3 grid((unsigned)S, (unsigned)C, (unsigned)(Fp / kChunk));
   const bool bin = (m->kind == NB_BERNOULLI);
   const int win = count_win(C);

@@ -331,14 +331,24 @@ constexpr int kReduceSplit = 8;
 
 // csum (or NULL): [RS][C] shares of S_c accumulated with integer atomics
 // (exact, so the order of the additions does not matter; one word per split
-// keeps the workgroups adding to one word few), from words the count kernel
-// cleared.
+// keeps the workgroups adding to one word few), then one word holding the OR
+// of the count kernel's n_flags flag words (an atomic OR only where a flag is
+// set); the count kernel cleared them.
 __global__ __launch_bounds__(256) void reduce_counts(const int64_t* __restrict__ part,
                                                     const int64_t* __restrict__ nc_part, int S, int C,
                                                     int F, int Fp, int64_t* __restrict__ part2,
-                                                    int64_t* __restrict__ nc2, int64_t* __restrict__ csum) {
+                                                    int64_t* __restrict__ nc2, int64_t* __restrict__ csum,
+                                                    const int32_t* __restrict__ flag_part, int n_flags) {
   const int c = blockIdx.y, rs = blockIdx.z, RS = gridDim.z;
   const int fl = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  if (csum) {
+    const int64_t nthreads = (int64_t)gridDim.x * gridDim.y * gridDim.z * 256;
+    int32_t bits = 0;
+    for (int64_t i = (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
+         i < n_flags; i += nthreads)
+      bits |= flag_part[i];
+    if (bits) atomicOr(reinterpret_cast<int*>(csum + (int64_t)RS * C), bits);
+  }
   const int f = blockIdx.x * 64 + fl;
   int64_t s = 0, m = 0;
   const int stride = 4 * RS;
@@ -593,9 +603,8 @@ __global__ __launch_bounds__(256) void tables_rows2(TableArgs a, const int64_t* 
   const int t = threadIdx.x;
   const int f = blockIdx.x * 256 + t;
   const int F = a.F, Fp = a.Fp;
-  int32_t fl = 0;
-  if (blockIdx.x == 0)
-    for (int i = t; i < a.n_flags; i += 256) fl |= a.flag_part[i];
+  // the OR of the count kernel's flags, gathered by reduce_counts
+  const int32_t fl = (blockIdx.x == 0 && t == 0) ? *reinterpret_cast<const int32_t*>(csum + (int64_t)a.RS * 2) : 0;
   int64_t v[2][kReduceSplit], w[2][kReduceSplit], u[2][kReduceSplit];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -643,14 +652,8 @@ __global__ __launch_bounds__(256) void tables_rows2(TableArgs a, const int64_t* 
     }
   }
   if (blockIdx.x == 0) {
-    int bits = fl & (kFlagOverflow | kFlagBadLabel | kFlagNegative | kFlagBadIndex);
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) bits |= __shfl_xor(bits, m);
-    __shared__ int red_b[4];
-    if ((t & 63) == 0) red_b[t >> 6] = bits;
-    __syncthreads();
     if (t == 0) {
-      bits = red_b[0] | red_b[1] | red_b[2] | red_b[3];
+      const int32_t bits = fl & (kFlagOverflow | kFlagBadLabel | kFlagNegative | kFlagBadIndex);
       const int64_t N = Nc[0] + Nc[1];
       double bias[2];
       int32_t flags = 0;
@@ -877,7 +880,8 @@ TrainWs train_ws(int32_t C, int32_t Fp, int64_t S) {
   w.off_part2_sq = take((size_t)w.RS * C * Fp * 8);
   // count-kernel flags [2][S][C][chunks] (counts, squares), then per-class flags
   w.off_flags = take(((size_t)2 * S * C * (Fp / kChunk) + C) * 4);
-  w.off_csum = take((size_t)w.RS * C * 8);   // class-sum shares of the one-launch two-class tables
+  // class-sum shares and the flag word of the one-launch two-class tables
+  w.off_csum = take((size_t)(w.RS * C + 1) * 8);
   w.total = off;
   return w;
 }
@@ -1088,7 +1092,7 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   const bool fused = (C == 2 && m->kind == NB_MULTINOMIAL && xtype == NB_X_U8);
   int64_t* csum = fused ? reinterpret_cast<int64_t*>(wsb + tw.off_csum) : nullptr;
   ca.zero_words = csum;
-  ca.n_zero = fused ? (int)(tw.RS * C) : 0;
+  ca.n_zero = fused ? (int)(tw.RS * C + 1) : 0;
   const dim3 grid((unsigned)S, (unsigned)C, (unsigned)(Fp / kChunk));
   const bool bin = (m->kind == NB_BERNOULLI);
   const int win = count_win(C);
@@ -1105,11 +1109,12 @@ int nb_train(nb_model* m, const void* x, int32_t xtype, int64_t n, int64_t ld, c
   }
 
   const dim3 rgrid((unsigned)((F + 63) / 64), (unsigned)C, (unsigned)tw.RS);
-  hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part, nc_part, (int)S, C, F, Fp, part2, nc2, csum);
+  hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part, nc_part, (int)S, C, F, Fp, part2, nc2, csum,
+                     flag_part, n_flags);
   NB_HIP_CHECK(hipGetLastError());
   if (gauss) {   // (the class totals it writes again are the same values)
     hipLaunchKernelGGL(reduce_counts, rgrid, dim3(256), 0, s, part_sq, nc_part, (int)S, C, F, Fp, part2_sq, nc2,
-                       nullptr);
+                       nullptr, nullptr, 0);
     NB_HIP_CHECK(hipGetLastError());
   }
 
